@@ -1,0 +1,15 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+Circuits, their tensor networks, contraction trees, sliced-index choices and
+output bitstrings.  Nothing here contracts tensors: it only builds the inputs
+that ``plan``/``contract`` and the oracle consume.
+"""
+from .circuits import (Circuit, random_grid_circuit, ghz_circuit, identity_circuit,
+                       mirror_circuit, coupling_pattern)
+from .network import Network, circuit_to_network
+from .planner import greedy_tree, tree_trimming, plan_network, tree_stats, node_label_sets
+from .bitstrings import random_bitstrings, all_bitstrings
+
+__all__ = ["Circuit", "random_grid_circuit", "ghz_circuit", "identity_circuit", "mirror_circuit",
+           "coupling_pattern", "Network", "circuit_to_network", "greedy_tree", "tree_trimming",
+           "plan_network", "tree_stats", "node_label_sets", "random_bitstrings", "all_bitstrings"]

@@ -1,0 +1,81 @@
+"""Circuit -> tensor network construction (input generator, Sec. II / Fig. 3).
+
+Each qubit starts as a rank-1 tensor |0> = (1, 0) carrying one open index.  A
+one-qubit gate becomes a rank-2 tensor T[out, in]; a two-qubit gate's 4x4
+matrix is reshaped to a rank-4 tensor T[a_out, b_out, a_in, b_in].  Gates are
+attached to the open indices of the qubits they act on, in circuit order, and
+the open index left on qubit q at the end is its output wire.  Index labels are
+non-negative integers, every label has dimension 2, and every label appears in
+exactly two tensors except output wires, which appear in one.
+
+Tensors are stored row-major in the order of their label tuple (first label
+slowest), which is the element order the C-ABI boundary expects.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .circuits import Circuit
+
+
+class Network:
+    def __init__(self, tensors, indices, output_labels, n_qubits, name="network"):
+        self.tensors = [np.ascontiguousarray(t, dtype=np.complex128) for t in tensors]
+        self.indices = [tuple(int(x) for x in ix) for ix in indices]
+        self.output_labels = [int(x) for x in output_labels]
+        self.n_qubits = int(n_qubits)
+        self.name = name
+        for t, ix in zip(self.tensors, self.indices):
+            assert t.shape == (2,) * len(ix), (t.shape, ix)
+
+    @property
+    def n_tensors(self) -> int:
+        return len(self.tensors)
+
+    def labels(self):
+        out = set()
+        for ix in self.indices:
+            out.update(ix)
+        return out
+
+    def label_count(self):
+        cnt = {}
+        for ix in self.indices:
+            for x in ix:
+                cnt[x] = cnt.get(x, 0) + 1
+        return cnt
+
+    def to_csr(self):
+        """Flat arrays for the C-ABI: (index_ptr, index_ids, data_ptr, data, output_index)."""
+        index_ptr = np.zeros(self.n_tensors + 1, dtype=np.int64)
+        data_ptr = np.zeros(self.n_tensors + 1, dtype=np.int64)
+        for i, (t, ix) in enumerate(zip(self.tensors, self.indices)):
+            index_ptr[i + 1] = index_ptr[i] + len(ix)
+            data_ptr[i + 1] = data_ptr[i] + t.size
+        index_ids = np.array([x for ix in self.indices for x in ix], dtype=np.int64)
+        data = np.concatenate([t.reshape(-1) for t in self.tensors]) if self.tensors else \
+            np.zeros(0, np.complex128)
+        data = np.ascontiguousarray(data.astype(np.complex128)).view(np.float64)
+        output_index = np.array(self.output_labels, dtype=np.int64)
+        return index_ptr, index_ids, data_ptr, data, output_index
+
+
+def circuit_to_network(circ: Circuit) -> Network:
+    n = circ.n_qubits
+    tensors, indices = [], []
+    next_label = 0
+    cur = []
+    for q in range(n):
+        tensors.append(np.array([1.0, 0.0], dtype=np.complex128))
+        indices.append((next_label,))
+        cur.append(next_label)
+        next_label += 1
+    for name, qs, m in circ.ops:
+        k = len(qs)
+        new = list(range(next_label, next_label + k))
+        next_label += k
+        tensors.append(m.reshape((2,) * (2 * k)))
+        indices.append(tuple(new) + tuple(cur[q] for q in qs))
+        for q, lab in zip(qs, new):
+            cur[q] = lab
+    return Network(tensors, indices, cur, n, name=circ.name)

@@ -1,0 +1,471 @@
+// C-ABI entry points and the plan executor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+#include "qxtn.h"
+
+using namespace qx;
+
+static thread_local std::string g_err;
+
+static qx_status fail(qx_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(QX_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct PendingEvent {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct qx_plan {
+  PlanCore pc;
+  bool timing = false;
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> pool;
+  qx_op_timing acc[QX_N_OPCLASS];
+  bool dry = true;
+  int device = 0;
+  QxCplx* d_leaves = nullptr;
+  char* d_arena = nullptr;
+  int64_t* d_gather = nullptr;
+  int64_t device_bytes = 0;
+};
+
+static int64_t plan_device_bytes(const PlanCore& pc) {
+  return ((pc.leaf_pool_elems * 8 + 255) / 256) * 256 + pc.arena_bytes +
+         (int64_t)pc.gathers.size() * pc.max_b * 8;
+}
+
+static QxCplx* tensor_ptr(qx_plan* p, int tid) {
+  const Tensor& t = p->pc.tensors[tid];
+  return t.is_leaf ? p->d_leaves + t.leaf_off : reinterpret_cast<QxCplx*>(p->d_arena + t.arena_off);
+}
+
+static const int64_t* gather_ptr(qx_plan* p, int g) {
+  return g < 0 ? nullptr : p->d_gather + (int64_t)g * p->pc.max_b;
+}
+
+static void resolve_pointers(qx_plan* p) {
+  for (Op& op : p->pc.ops) {
+    QxCplx* a = op.in_a >= 0 ? tensor_ptr(p, op.in_a) : nullptr;
+    QxCplx* b = op.in_b >= 0 ? tensor_ptr(p, op.in_b) : nullptr;
+    QxCplx* c = tensor_ptr(p, op.out);
+    switch (op.kind) {
+      case OP_SIMT:
+        op.simt.a = a; op.simt.b = b; op.simt.c = c;
+        op.simt.a_gather = gather_ptr(p, op.gather_a);
+        op.simt.b_gather = gather_ptr(p, op.gather_b);
+        break;
+      case OP_GEMM:
+        op.gemm.a = a; op.gemm.b = b; op.gemm.c = c;
+        op.gemm.a_gather = gather_ptr(p, op.gather_a);
+        op.gemm.b_gather = gather_ptr(p, op.gather_b);
+        break;
+      case OP_DOT:
+        op.dot.a = a; op.dot.b = b; op.dot.c = c;
+        op.dot.a_gather = gather_ptr(p, op.gather_a);
+        op.dot.b_gather = gather_ptr(p, op.gather_b);
+        break;
+      case OP_PERM:
+        op.perm.in = a; op.perm.out = c;
+        break;
+    }
+  }
+}
+
+static hipEvent_t take_event(qx_plan* p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch through f(), bracketed by events when timing is enabled.
+template <class F>
+static hipError_t timed(qx_plan* p, int cls, double flops, double bytes, hipStream_t s, F f) {
+  if (!p->timing) return f();
+  PendingEvent ev{cls, take_event(p), take_event(p), flops, bytes};
+  if (!ev.a || !ev.b) return hipErrorOutOfMemory;
+  hipEventRecord(ev.a, s);
+  hipError_t e = f();
+  hipEventRecord(ev.b, s);
+  p->pending.push_back(ev);
+  return e;
+}
+
+static int op_class(int kind) {
+  switch (kind) {
+    case OP_GEMM: return QX_OPCLASS_GEMM;
+    case OP_DOT: return QX_OPCLASS_DOT;
+    case OP_PERM: return QX_OPCLASS_PERMUTE;
+    default: return QX_OPCLASS_SIMT;
+  }
+}
+
+static int64_t fix_offset(const std::vector<FixTerm>& fx, int64_t sbase) {
+  int64_t off = 0;
+  for (const FixTerm& f : fx)
+    if ((sbase >> f.j) & 1) off += f.stride;
+  return off;
+}
+
+static qx_status run_op(qx_plan* p, const Op& op, int B, int64_t sbase, hipStream_t s) {
+  const bool outb = p->pc.tensors[op.out].batched;
+  const int64_t fa = fix_offset(op.fix_a, sbase), fb = fix_offset(op.fix_b, sbase);
+  const double scale = outb ? (double)B / p->pc.max_b : 1.0;
+  hipError_t e = timed(p, op_class(op.kind), op.flops * scale, op.bytes * scale, s, [&]() -> hipError_t {
+  switch (op.kind) {
+    case OP_SIMT: {
+      SimtArgs a = op.simt;
+      a.a += fa; a.b += fb;
+      if (outb) a.n_items = B;
+      return launch_simt(a, s);
+    }
+    case OP_GEMM: {
+      GemmArgs g = op.gemm;
+      g.a += fa; g.b += fb;
+      if (outb) g.n_items = B;
+      return launch_gemm(g, p->pc.precision, op.tile, s);
+    }
+    case OP_DOT: {
+      DotArgs d = op.dot;
+      d.a += fa; d.b += fb;
+      if (outb) d.n_items = B;
+      return launch_dot(d, s);
+    }
+    case OP_PERM: {
+      PermArgs q = op.perm;
+      q.in += fa;
+      if (outb) q.n_items = B;
+      return launch_permute(q, s);
+    }
+  }
+  return hipErrorInvalidValue;
+  });
+  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return QX_OK;
+}
+
+// Estimated seconds for a whole slice range: matrix-core work, plus a launch cost per op.
+static double est_cost(const PlanCore& pc) {
+  const double blocks = std::ldexp(1.0, pc.n_sliced - pc.js);
+  const double flops = pc.flops_block * blocks + pc.flops_call;
+  return flops / 60e12 + blocks * (pc.n_block + 1) * 6e-6 + pc.n_call * 6e-6;
+}
+
+extern "C" {
+
+const char* qx_last_error(void) { return g_err.c_str(); }
+
+qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64_t* sliced,
+                         int32_t n_sliced, const qx_plan_options* opt_in, void* stream,
+                         qx_plan** out) {
+  g_err.clear();
+  if (!out) return fail(QX_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!net) return fail(QX_ERR_INVALID_ARG, "net is NULL");
+  if (net->n_tensors < 1) return fail(QX_ERR_INVALID_NETWORK, "network has no tensors");
+  if (!net->index_ptr || !net->data_ptr || !net->data) return fail(QX_ERR_INVALID_ARG, "network arrays are NULL");
+  if (net->index_ptr[net->n_tensors] > 0 && !net->index_ids) return fail(QX_ERR_INVALID_ARG, "index_ids is NULL");
+  if (net->n_qubits < 0 || net->n_qubits > 64) return fail(QX_ERR_UNSUPPORTED, "n_qubits must be in 0..64");
+  if (net->n_qubits > 0 && !net->output_index) return fail(QX_ERR_INVALID_ARG, "output_index is NULL");
+  if (net->n_tensors > 1 && !tree) return fail(QX_ERR_INVALID_ARG, "tree is NULL");
+  if (n_sliced < 0 || n_sliced > 40) return fail(QX_ERR_UNSUPPORTED, "n_sliced must be in 0..40");
+  if (n_sliced > 0 && !sliced) return fail(QX_ERR_INVALID_ARG, "sliced is NULL");
+  for (int t = 0; t < net->n_tensors; ++t) {
+    const int64_t r = net->index_ptr[t + 1] - net->index_ptr[t];
+    if (r < 0 || r > 40) return fail(QX_ERR_UNSUPPORTED, "tensor rank must be in 0..40");
+  }
+  qx_plan_options opt = {QX_C64, 1, -1, 0, 0};
+  if (opt_in) opt = *opt_in;
+  if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
+    return fail(QX_ERR_INVALID_ARG, "unknown precision");
+  if (opt.max_bitstrings < 1 || opt.max_bitstrings > (1 << 20))
+    return fail(QX_ERR_INVALID_ARG, "max_bitstrings must be in 1..2^20");
+  if (opt.slice_batch_log2 < -1 || opt.slice_batch_log2 > std::min(n_sliced, QX_MAX_SBITS))
+    return fail(QX_ERR_INVALID_ARG, "slice_batch_log2 must be -1 or in 0..min(n_sliced, 24)");
+  if (opt.hbm_budget_bytes < 0) return fail(QX_ERR_INVALID_ARG, "hbm_budget_bytes < 0");
+
+  qx_plan* p = new (std::nothrow) qx_plan();
+  if (!p) return fail(QX_ERR_INVALID_ARG, "out of host memory");
+  std::string err;
+  qx_status st;
+  if (opt.slice_batch_log2 >= 0) {
+    st = compile_plan(net, tree, sliced, n_sliced, opt, opt.slice_batch_log2, p->pc, err);
+  } else {
+    const int64_t limit = opt.hbm_budget_bytes > 0 ? opt.hbm_budget_bytes : (int64_t)96 << 30;
+    double best = 1e300;
+    int best_js = -1;
+    st = QX_OK;
+    for (int js = 0; js <= std::min(n_sliced, 8); ++js) {
+      PlanCore cand;
+      st = compile_plan(net, tree, sliced, n_sliced, opt, js, cand, err);
+      if (st != QX_OK) break;
+      if (plan_device_bytes(cand) > limit && js > 0) continue;
+      const double c = est_cost(cand);
+      if (c < best * 0.97 || best_js < 0) {
+        best = c;
+        best_js = js;
+      }
+    }
+    if (st == QX_OK) st = compile_plan(net, tree, sliced, n_sliced, opt, best_js < 0 ? 0 : best_js, p->pc, err);
+  }
+  if (st != QX_OK) {
+    delete p;
+    return fail(st, err);
+  }
+  p->device_bytes = plan_device_bytes(p->pc);
+  if (opt.hbm_budget_bytes > 0 && p->device_bytes > opt.hbm_budget_bytes) {
+    const int64_t need = p->device_bytes;
+    delete p;
+    return fail(QX_ERR_OUT_OF_BUDGET, "plan needs " + std::to_string(need) + " device bytes, budget is " +
+                                          std::to_string(opt.hbm_budget_bytes));
+  }
+  p->dry = opt.dry_run != 0;
+  if (!p->dry) {
+    hipStream_t s = (hipStream_t)stream;
+    auto cleanup = [&](qx_status code, const std::string& m) {
+      qx_plan_destroy(p);
+      return fail(code, m);
+    };
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return cleanup(QX_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    const int64_t leaf_bytes = std::max<int64_t>(256, p->pc.leaf_pool_elems * 8);
+    if ((e = hipMalloc((void**)&p->d_leaves, leaf_bytes)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMalloc(leaves): ") + hipGetErrorString(e));
+    if ((e = hipMalloc((void**)&p->d_arena, std::max<int64_t>(256, p->pc.arena_bytes))) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMalloc(arena): ") + hipGetErrorString(e));
+    const int64_t gb = std::max<int64_t>(256, (int64_t)p->pc.gathers.size() * p->pc.max_b * 8);
+    if ((e = hipMalloc((void**)&p->d_gather, gb)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMalloc(gather): ") + hipGetErrorString(e));
+    // leaves: complex128 -> complex64, round to nearest even
+    std::vector<float> h(2 * p->pc.leaf_pool_elems);
+    for (size_t i = 0; i < h.size(); ++i) h[i] = (float)p->pc.leaf_data[i];
+    if ((e = hipMemcpyAsync(p->d_leaves, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMemcpyAsync(leaves): ") + hipGetErrorString(e));
+    resolve_pointers(p);
+    for (int i = 0; i < p->pc.n_const; ++i) {
+      qx_status r = run_op(p, p->pc.ops[i], 1, 0, s);
+      if (r != QX_OK) {
+        std::string m = g_err;
+        return cleanup(r, m);
+      }
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("plan pre-contraction: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return QX_OK;
+}
+
+qx_status qx_plan_get_info(const qx_plan* p, qx_plan_info* info) {
+  g_err.clear();
+  if (!p || !info) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  const PlanCore& pc = p->pc;
+  std::memset(info, 0, sizeof(*info));
+  info->device_bytes = p->device_bytes;
+  info->arena_bytes = pc.arena_bytes;
+  info->n_leaves = pc.n_leaves;
+  info->n_sliced = pc.n_sliced;
+  info->slice_batch_log2 = pc.js;
+  info->width = pc.width;
+  info->n_ops_const = pc.n_const;
+  info->n_ops_call = pc.n_call;
+  info->n_ops_block = pc.n_block;
+  info->n_gemm_block = pc.n_gemm_block;
+  info->flops_per_slice = pc.flops_per_slice;
+  info->flops_block = pc.flops_block;
+  info->gemm_flops_block = pc.gemm_flops_block;
+  info->flops_call = pc.flops_call;
+  return QX_OK;
+}
+
+qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64_t slice_begin,
+                      int64_t slice_end, double* d_amplitudes, void* stream) {
+  g_err.clear();
+  if (!p) return fail(QX_ERR_INVALID_ARG, "plan is NULL");
+  const PlanCore& pc = p->pc;
+  if (B < 1 || B > pc.max_b)
+    return fail(QX_ERR_INVALID_ARG, "B must be in 1..max_bitstrings (" + std::to_string(pc.max_b) + ")");
+  const int64_t nsl = (int64_t)1 << pc.n_sliced;
+  if (slice_begin < 0 || slice_end < slice_begin || slice_end > nsl)
+    return fail(QX_ERR_INVALID_ARG, "slice range must satisfy 0 <= begin <= end <= 2^n_sliced");
+  if (!d_amplitudes) return fail(QX_ERR_INVALID_ARG, "d_amplitudes is NULL");
+  if (!d_bitstrings) return fail(QX_ERR_INVALID_ARG, "d_bitstrings is NULL");
+  if (p->dry) return fail(QX_ERR_DRY_RUN, "plan was compiled with dry_run");
+  if (slice_begin == slice_end) return QX_OK;
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != p->device) return fail(QX_ERR_INVALID_ARG, "current device differs from the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  for (size_t g = 0; g < pc.gathers.size(); ++g) {
+    const GatherDesc& gd = pc.gathers[g];
+    GatherArgs ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.x = d_bitstrings;
+    ga.out = p->d_gather + (int64_t)g * pc.max_b;
+    ga.n_items = B;
+    ga.n_q = (int)gd.q.size();
+    for (size_t j = 0; j < gd.q.size(); ++j) {
+      ga.q[j] = gd.q[j];
+      ga.stride[j] = gd.stride[j];
+    }
+    hipError_t e = timed(p, QX_OPCLASS_GATHER, 0.0, 16.0 * B, s, [&] { return launch_gather(ga, s); });
+    if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("gather launch: ") + hipGetErrorString(e));
+  }
+  for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
+    qx_status r = run_op(p, pc.ops[i], B, 0, s);
+    if (r != QX_OK) return r;
+  }
+  const int64_t bsz = (int64_t)1 << pc.js;
+  const int64_t first = slice_begin >> pc.js, last = (slice_end - 1) >> pc.js;
+  const Tensor& rt = pc.tensors[pc.root];
+  for (int64_t bb = first; bb <= last; ++bb) {
+    const int64_t base = bb << pc.js;
+    for (int i = pc.n_const + pc.n_call; i < (int)pc.ops.size(); ++i) {
+      qx_status r = run_op(p, pc.ops[i], B, base, s);
+      if (r != QX_OK) return r;
+    }
+    SliceSumArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.root = tensor_ptr(p, pc.root);
+    sa.root_item = rt.batched ? rt.elems() : 0;
+    sa.root_gather = gather_ptr(p, pc.root_gather);
+    sa.amp = d_amplitudes;
+    sa.n_items = B;
+    sa.n_sbits = pc.js;
+    sa.s_lo = (int)(std::max(slice_begin, base) - base);
+    sa.s_hi = (int)(std::min(slice_end, base + bsz) - base);
+    for (int j = 0; j < pc.js; ++j) sa.s_stride[j] = pc.root_sstride[j];
+    const double sbytes = 8.0 * (sa.s_hi - sa.s_lo) * B + 16.0 * 2 * B;
+    hipError_t e = timed(p, QX_OPCLASS_SLICESUM, 0.0, sbytes, s, [&] { return launch_slice_sum(sa, s); });
+    if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("slice-sum launch: ") + hipGetErrorString(e));
+  }
+  return QX_OK;
+}
+
+qx_status qx_plan_set_timing(qx_plan* p, int32_t enable) {
+  g_err.clear();
+  if (!p) return fail(QX_ERR_INVALID_ARG, "plan is NULL");
+  if (p->dry && enable) return fail(QX_ERR_DRY_RUN, "plan was compiled with dry_run");
+  p->timing = enable != 0;
+  return QX_OK;
+}
+
+qx_status qx_plan_get_timing(qx_plan* p, qx_op_timing* out, int32_t reset) {
+  g_err.clear();
+  if (!p || !out) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  for (PendingEvent& ev : p->pending) {
+    HIP_TRY(hipEventSynchronize(ev.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+    qx_op_timing& t = p->acc[ev.cls];
+    t.launches += 1;
+    t.seconds += ms * 1e-3;
+    t.flops += ev.flops;
+    t.bytes += ev.bytes;
+    p->pool.push_back(ev.a);
+    p->pool.push_back(ev.b);
+  }
+  p->pending.clear();
+  for (int i = 0; i < QX_N_OPCLASS; ++i) out[i] = p->acc[i];
+  if (reset) std::memset(p->acc, 0, sizeof(p->acc));
+  return QX_OK;
+}
+
+void qx_plan_destroy(qx_plan* p) {
+  if (!p) return;
+  if (!p->dry) {
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    for (PendingEvent& ev : p->pending) {
+      hipEventDestroy(ev.a);
+      hipEventDestroy(ev.b);
+    }
+    for (hipEvent_t e : p->pool) hipEventDestroy(e);
+    if (p->d_leaves) hipFree(p->d_leaves);
+    if (p->d_arena) hipFree(p->d_arena);
+    if (p->d_gather) hipFree(p->d_gather);
+    hipSetDevice(cur);
+  }
+  delete p;
+}
+
+qx_status qx_permute_c64(const void* d_in, void* d_out, int32_t rank, const int32_t* in_pos, int64_t items,
+                         void* stream) {
+  g_err.clear();
+  if (!d_in || !d_out || !in_pos) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  if (rank < 0 || rank > 40) return fail(QX_ERR_UNSUPPORTED, "rank must be in 0..40");
+  if (items < 0 || items > 65535) return fail(QX_ERR_INVALID_ARG, "items must be in 0..65535");
+  uint64_t seen = 0;
+  for (int i = 0; i < rank; ++i) {
+    if (in_pos[i] < 0 || in_pos[i] >= rank || ((seen >> in_pos[i]) & 1))
+      return fail(QX_ERR_INVALID_ARG, "in_pos is not a permutation of 0..rank-1");
+    seen |= 1ULL << in_pos[i];
+  }
+  if (items == 0) return QX_OK;
+  PermArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = (const QxCplx*)d_in;
+  a.out = (QxCplx*)d_out;
+  a.rank = rank;
+  a.n_items = (int)items;
+  a.in_item = a.out_item = (int64_t)1 << rank;
+  for (int i = 0; i < rank; ++i) a.in_pos[i] = in_pos[i];
+  HIP_TRY(launch_permute(a, (hipStream_t)stream));
+  return QX_OK;
+}
+
+qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K, int64_t a_ms,
+                   int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a, int64_t stride_b,
+                   int64_t stride_c, int64_t batch, int32_t precision, void* stream) {
+  g_err.clear();
+  if (!d_a || !d_b || !d_c) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  if (M < 1 || N < 1 || K < 1 || batch < 0) return fail(QX_ERR_INVALID_ARG, "M, N, K must be >= 1, batch >= 0");
+  if (!(a_ms == 1 || a_ks == 1) || !(b_ks == 1 || b_ns == 1) || a_ms < 1 || a_ks < 1 || b_ks < 1 || b_ns < 1)
+    return fail(QX_ERR_INVALID_ARG, "one stride of each operand must be 1 and all strides >= 1");
+  if (precision < QX_C64 || precision > QX_SPLIT_FP16) return fail(QX_ERR_INVALID_ARG, "unknown precision");
+  if (batch > 0x7fffffff) return fail(QX_ERR_INVALID_ARG, "batch too large");
+  if (batch == 0) return QX_OK;
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.a = (const QxCplx*)d_a;
+  g.b = (const QxCplx*)d_b;
+  g.c = (QxCplx*)d_c;
+  g.M = M; g.N = N; g.K = K;
+  g.a_ms = a_ms; g.a_ks = a_ks; g.b_ks = b_ks; g.b_ns = b_ns; g.c_ms = N;
+  g.a_item = stride_a; g.b_item = stride_b; g.c_item = stride_c;
+  g.n_items = (int)batch;
+  g.nh = 0;
+  // 16-byte vector loads along k need even strides and an aligned base
+  g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
+  g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
+  const int tile = (M >= 128 && N >= 128) ? GEMM_TILE_128x128 : GEMM_TILE_64x64;
+  HIP_TRY(launch_gemm(g, precision, tile, (hipStream_t)stream));
+  return QX_OK;
+}
+
+}  // extern "C"

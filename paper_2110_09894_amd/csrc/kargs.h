@@ -1,0 +1,90 @@
+// Kernel argument blocks shared by the plan compiler (host) and the HIP kernels.
+//
+// Every tensor is a dense array of complex64 (float2) whose indices all have
+// dimension 2, so an element's offset is a sum of per-index ("bit") strides.
+// A tensor may also carry a batch dimension over bitstrings ("items").
+// Operands are addressed as
+//   base + item * item_stride + gather[item] + sum_i bit_i(index) * stride_i
+// where gather[] holds, per bitstring, the offset selected by that bitstring's
+// qubit values on the operand's open output indices (output closure, Sec. II),
+// and base already includes the offset chosen by the fixed sliced indices of
+// the current slice (Eq. 2).
+#pragma once
+#include <stdint.h>
+
+#define QX_MAX_BITS 48      // bits of one tensor (incl. open output and slice bits)
+#define QX_MAX_KBITS 24     // contracted bits of one small contraction
+#define QX_MAX_HBITS 16     // shared slice bits of one matrix product (batch)
+#define QX_MAX_SBITS 24     // slice bits carried to the root
+
+struct QxCplx { float x, y; };
+
+// Small / memory-bound contraction, one thread per output element:
+//   C[item][o] = sum_k A[..o..k] * B[..o..k]     (C dense in o)
+struct SimtArgs {
+  const QxCplx *a, *b;
+  QxCplx *c;
+  int64_t a_item, b_item, c_item;        // item strides (0 = operand shared by all items)
+  const int64_t *a_gather, *b_gather;    // per-item offsets, or null
+  int32_t n_out, n_k, n_items;
+  int32_t pad_;
+  int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];   // strides of output bit i (0 if absent)
+  int64_t a_ks[QX_MAX_KBITS], b_ks[QX_MAX_KBITS]; // strides of contracted bit j
+};
+
+// Batched complex matrix product on the matrix cores:
+//   C[z][m][n] = sum_k A[z][m][k] B[z][k][n],  z = item * 2^nh + h
+struct GemmArgs {
+  const QxCplx *a, *b;
+  QxCplx *c;
+  int64_t M, N, K;
+  int64_t a_ms, a_ks, b_ks, b_ns, c_ms;  // c_ns == 1; one of (a_ms, a_ks) and of (b_ks, b_ns) is 1
+  int64_t a_item, b_item, c_item;
+  const int64_t *a_gather, *b_gather;
+  int32_t n_items, nh;                   // nh = number of shared-slice bits
+  int32_t vec_a, vec_b;                  // 16-byte vector loads allowed along k (alignment)
+  int32_t pad_;
+  int64_t a_hs[QX_MAX_HBITS], b_hs[QX_MAX_HBITS], c_hs[QX_MAX_HBITS];
+};
+
+// Long inner products (root of a slice's tree): one work-group per output element.
+//   C[item][o] = sum_{k<K} A[..o..][k] * B[..o..][k]   (k contiguous in both)
+struct DotArgs {
+  const QxCplx *a, *b;
+  QxCplx *c;
+  int64_t K;
+  int64_t a_item, b_item, c_item;
+  const int64_t *a_gather, *b_gather;
+  int32_t n_out, n_items;
+  int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];
+};
+
+// Bit permutation: out[item][o] = in[item][sum_i bit_i(o) << in_pos[i]]
+struct PermArgs {
+  const QxCplx *in;
+  QxCplx *out;
+  int64_t in_item, out_item;
+  int32_t rank, n_items;
+  int32_t in_pos[QX_MAX_BITS];
+};
+
+// Sum over the slices of one block, FP64, ascending slice order:
+//   amp[item] += sum_{s in [s_lo, s_hi)} root[item-offset + sum_j bit_j(s) * s_stride[j]]
+struct SliceSumArgs {
+  const QxCplx *root;
+  int64_t root_item;
+  const int64_t *root_gather;
+  double *amp;                          // [items][2]
+  int32_t n_items, n_sbits;
+  int32_t s_lo, s_hi;
+  int64_t s_stride[QX_MAX_SBITS];
+};
+
+// Per-bitstring gather offsets: out[item] = sum_j bit_{q_j}(x[item]) * stride_j
+struct GatherArgs {
+  const uint64_t *x;
+  int64_t *out;
+  int32_t n_items, n_q;
+  int32_t q[64];
+  int64_t stride[64];
+};

@@ -1,0 +1,145 @@
+"""The C-ABI library loads, exports what include/qxtn.h declares, and validates
+its inputs on the host (dry-run plans; no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_09894_amd import qxtn
+from workloads import (circuit_to_network, random_grid_circuit, greedy_tree, tree_trimming, tree_stats,
+                       Network, ghz_circuit)
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qxtn.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qx_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qxtn.lib()
+    names = _declared()
+    assert set(names) == set(qxtn.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _small():
+    circ = random_grid_circuit(2, 3, 4, 5)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=1)
+    sl = tree_trimming(net, tree, 3, seed=1)
+    return net, tree, sl
+
+
+def test_dry_run_plan_info_matches_tree_stats():
+    net, tree, sl = _small()
+    p = qxtn.Plan(net, tree, sl, max_bitstrings=8, dry_run=True)
+    info = p.info()
+    st = tree_stats(net, tree, sl)
+    assert info["n_leaves"] == net.n_tensors
+    assert info["n_sliced"] == 3
+    assert info["width"] == st["width"]
+    assert info["flops_per_slice"] == pytest.approx(st["flops_per_slice"])
+    assert info["n_ops_const"] + info["n_ops_call"] + info["n_ops_block"] >= net.n_tensors - 1
+
+
+@pytest.mark.parametrize("rows,cols,depth,k,B", [(3, 4, 8, 0, 64), (5, 6, 12, 10, 256), (4, 5, 8, 4, 16)])
+def test_dry_run_configs_compile(rows, cols, depth, k, B):
+    net = circuit_to_network(random_grid_circuit(rows, cols, depth, 2))
+    tree = greedy_tree(net, seed=3)
+    sl = tree_trimming(net, tree, k, seed=3) if k else []
+    for js in range(0, min(k, 3) + 1):
+        p = qxtn.Plan(net, tree, sl, max_bitstrings=B, slice_batch_log2=js, dry_run=True)
+        assert p.info()["slice_batch_log2"] == js
+
+
+def test_contract_on_dry_run_plan_is_refused():
+    net, tree, sl = _small()
+    p = qxtn.Plan(net, tree, sl, dry_run=True)
+
+    class _T:
+        shape = (1,)
+
+        def data_ptr(self):
+            return 1024
+
+    with pytest.raises(qxtn.QxError) as e:
+        p.contract(_T(), _T())
+    assert e.value.status == qxtn.QX_ERR_DRY_RUN
+
+
+def _expect(status, fn):
+    with pytest.raises(qxtn.QxError) as e:
+        fn()
+    assert e.value.status == status, e.value
+
+
+def test_bad_tree_rejected():
+    net, tree, sl = _small()
+    bad = np.array(tree).copy()
+    bad[3] = bad[2]  # consume the same ids twice
+    _expect(qxtn.QX_ERR_INVALID_TREE, lambda: qxtn.Plan(net, bad, sl, dry_run=True))
+    fwd = np.array(tree).copy()
+    fwd[0, 0] = 10 ** 6  # undefined id
+    _expect(qxtn.QX_ERR_INVALID_TREE, lambda: qxtn.Plan(net, fwd, sl, dry_run=True))
+
+
+def test_label_used_three_times_rejected():
+    net, tree, sl = _small()
+    idx = [list(ix) for ix in net.indices]
+    idx[-1][0] = idx[-2][0] if idx[-2][0] != idx[-1][0] else idx[-3][0]
+    bad = Network(net.tensors, idx, net.output_labels, net.n_qubits)
+    _expect(qxtn.QX_ERR_INVALID_NETWORK, lambda: qxtn.Plan(bad, tree, [], dry_run=True))
+
+
+def test_dimension_other_than_two_rejected():
+    net, tree, sl = _small()
+
+    class Bad:
+        def to_csr(self):
+            ip, ii, dp, d, oi = net.to_csr()
+            dp = dp.copy()
+            dp[1:] += 1  # first tensor claims 3 elements for rank 1
+            d = np.concatenate([d[:2], [0.0, 0.0], d[2:]])
+            return ip, ii, dp, d, oi
+
+    _expect(qxtn.QX_ERR_UNSUPPORTED, lambda: qxtn.Plan(Bad(), tree, [], dry_run=True))
+
+
+def test_sliced_output_wire_rejected():
+    net, tree, sl = _small()
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, [net.output_labels[0]], dry_run=True))
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, [sl[0], sl[0]], dry_run=True))
+
+
+def test_budget_too_small_rejected():
+    net, tree, sl = _small()
+    _expect(qxtn.QX_ERR_OUT_OF_BUDGET,
+            lambda: qxtn.Plan(net, tree, sl, max_bitstrings=8, hbm_budget_bytes=64, dry_run=True))
+
+
+def test_bad_options_rejected():
+    net, tree, sl = _small()
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, sl, precision=7, dry_run=True))
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, sl, max_bitstrings=0, dry_run=True))
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, sl, slice_batch_log2=4, dry_run=True))
+
+
+def test_single_tensor_and_ghz_plans():
+    one = Network([np.array([0.6, 0.8j])], [(7,)], [7], 1)
+    qxtn.Plan(one, np.zeros((0, 2), np.int32), [], dry_run=True)
+    net = circuit_to_network(ghz_circuit(49))
+    p = qxtn.Plan(net, greedy_tree(net), [], max_bitstrings=4, dry_run=True)
+    assert p.info()["width"] == 2
+
+
+def test_error_message_is_set():
+    net, tree, sl = _small()
+    try:
+        qxtn.Plan(net, tree, [net.output_labels[0]], dry_run=True)
+    except qxtn.QxError:
+        pass
+    assert "output wire" in qxtn.last_error()

@@ -1,0 +1,79 @@
+"""Kernel-level GPU tests through the C-ABI: the LDS-tiled permute is bit-exact
+against numpy.transpose, the matrix-core complex GEMM is within FP32
+accumulation bounds of a complex128 product."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2110_09894_amd import qxtn  # noqa: E402
+
+
+def _c64(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.float32)).cuda()
+
+
+def _host_c64(t):
+    return t.cpu().numpy().view(np.complex64)
+
+
+@pytest.mark.parametrize("rank,items,seed", [(1, 1, 0), (3, 2, 1), (5, 1, 2), (8, 3, 3), (10, 1, 4),
+                                             (13, 2, 5), (18, 1, 6), (21, 1, 7)])
+def test_permute_bit_exact(rank, items, seed):
+    rng = np.random.default_rng(seed)
+    in_pos = rng.permutation(rank).astype(np.int32)
+    x = _c64(rng, items, 2 ** rank)
+    out = torch.empty_like(_dev(x))
+    qxtn.permute_c64(_dev(x), out, in_pos, items)
+    torch.cuda.synchronize()
+    got = _host_c64(out).reshape(items, 2 ** rank)
+    # axis a of the (2,)*rank view is bit rank-1-a; output bit i comes from input bit in_pos[i]
+    xt = x.reshape((items,) + (2,) * rank)
+    axes = [0] + [1 + rank - 1 - int(in_pos[rank - 1 - a]) for a in range(rank)]
+    want = np.transpose(xt, axes).reshape(items, 2 ** rank)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_permute_identity_and_reversal():
+    rng = np.random.default_rng(9)
+    x = _c64(rng, 1, 2 ** 12)
+    for in_pos in (np.arange(12), np.arange(12)[::-1]):
+        out = torch.empty_like(_dev(x))
+        qxtn.permute_c64(_dev(x), out, in_pos.astype(np.int32), 1)
+        torch.cuda.synchronize()
+        want = np.transpose(x.reshape((1,) + (2,) * 12), [0] + [1 + 11 - int(in_pos[11 - a]) for a in range(12)])
+        assert np.array_equal(_host_c64(out).reshape(-1), want.reshape(-1))
+
+
+def _gemm_case(M, N, K, akc, bkc, batch, seed, precision="c64"):
+    rng = np.random.default_rng(seed)
+    A = _c64(rng, batch, M, K)
+    Bm = _c64(rng, batch, K, N)
+    a_store = A if akc else np.ascontiguousarray(np.swapaxes(A, 1, 2))
+    b_store = np.ascontiguousarray(np.swapaxes(Bm, 1, 2)) if bkc else Bm
+    a_ms, a_ks = (K, 1) if akc else (1, M)
+    b_ks, b_ns = (1, K) if bkc else (N, 1)
+    dc = torch.zeros(batch * M * N * 2, dtype=torch.float32, device="cuda")
+    qxtn.cgemm(_dev(a_store), _dev(b_store), dc, M, N, K, a_ms, a_ks, b_ks, b_ns, M * K, K * N, M * N, batch,
+               precision)
+    torch.cuda.synchronize()
+    got = _host_c64(dc).reshape(batch, M, N).astype(np.complex128)
+    want = np.matmul(A.astype(np.complex128), Bm.astype(np.complex128))
+    bound = np.matmul(np.abs(A).astype(np.float64), np.abs(Bm).astype(np.float64))
+    return got, want, bound
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 128), (256, 512, 64), (64, 64, 16), (37, 53, 19), (1, 1, 1),
+                                   (300, 129, 257), (32, 2048, 32), (512, 512, 512)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (True, False), (False, True), (False, False)])
+def test_cgemm_c64(M, N, K, akc, bkc):
+    got, want, bound = _gemm_case(M, N, K, akc, bkc, 2, M * 7 + N * 3 + K)
+    # FP32 accumulation: |err| <= K * 2^-23 * (|A||B|) componentwise, with margin
+    assert np.all(np.abs(got - want) <= 2 * K * 2.0 ** -23 * bound + 1e-30)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < 2e-6

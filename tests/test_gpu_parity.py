@@ -1,0 +1,156 @@
+"""End-to-end parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerance for complex64: max_b |a_b - ref_b| <= 1e-5 * rms_b |ref_b| over the
+request's bitstrings (relative error against the batch's amplitude scale, so
+near-zero amplitudes do not make the criterion meaningless).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2110_09894_amd import qxtn  # noqa: E402
+from workloads import (circuit_to_network, random_grid_circuit, ghz_circuit, identity_circuit,  # noqa: E402
+                       mirror_circuit, greedy_tree, tree_trimming, all_bitstrings, random_bitstrings,
+                       configs)
+from tests._util import rms_err, gpu_amplitudes  # noqa: E402
+
+TOL_C64 = 1e-5
+
+
+def test_c1_all_64_amplitudes():
+    w = configs.get("c1")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs))
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_statevector(w.circuit(), xs)
+    assert rms_err(got, want) < TOL_C64
+
+
+def test_c1_deterministic_bitwise():
+    w = configs.get("c1")
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs))
+    a = gpu_amplitudes(plan, xs)
+    b = gpu_amplitudes(plan, xs)
+    assert np.array_equal(a.view(np.float64), b.view(np.float64))
+
+
+def test_normalisation_all_4096_bitstrings():
+    w = configs.get("c1")
+    tree, sl, _ = w.plan_inputs()
+    xs = all_bitstrings(12)
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs))
+    got = gpu_amplitudes(plan, xs)
+    assert abs(np.sum(np.abs(got) ** 2) - 1.0) < 1e-5
+    want = oracle.statevector(w.circuit()).transpose(list(range(11, -1, -1))).reshape(-1)
+    assert rms_err(got, want) < TOL_C64
+
+
+@pytest.mark.parametrize("js", [0, 1, 3, 4])
+def test_sliced_small_network_all_js(js):
+    circ = random_grid_circuit(3, 3, 6, 21)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=2)
+    sl = tree_trimming(net, tree, 4, seed=2)
+    xs = random_bitstrings(9, 16, 5)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=16, slice_batch_log2=js)
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_statevector(circ, xs)
+    assert rms_err(got, want) < TOL_C64
+    want3 = oracle.amplitudes_sliced(net, tree, xs, sl)
+    assert rms_err(got, want3) < TOL_C64
+
+
+def test_ragged_slice_ranges_and_additivity():
+    circ = random_grid_circuit(3, 4, 6, 22)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=4)
+    sl = tree_trimming(net, tree, 5, seed=4)
+    xs = random_bitstrings(12, 8, 6)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=8, slice_batch_log2=2)
+    full = gpu_amplitudes(plan, xs)
+    parts = gpu_amplitudes(plan, xs, (0, 13)) + gpu_amplitudes(plan, xs, (13, 32))
+    assert rms_err(parts, full) < 1e-6
+    rag = gpu_amplitudes(plan, xs, (3, 11))
+    want = np.array([oracle.amplitude_sliced(net, tree, x, sl, (3, 11)) for x in xs])
+    assert rms_err(rag, want) < TOL_C64
+    empty = gpu_amplitudes(plan, xs, (7, 7))
+    assert np.all(empty == 0)
+    # B smaller than max_bitstrings, and a single bitstring
+    one = gpu_amplitudes(plan, xs[:1])
+    assert abs(one[0] - full[0]) <= 1e-6 * np.sqrt(np.mean(np.abs(full) ** 2))
+
+
+def test_ghz_49_qubits():
+    net = circuit_to_network(ghz_circuit(49))
+    tree = greedy_tree(net)
+    ones = (1 << 49) - 1
+    xs = np.array([0, ones, 1, 12345678901], dtype=np.uint64)
+    plan = qxtn.Plan(net, tree, [], max_bitstrings=4)
+    got = gpu_amplitudes(plan, xs)
+    s = 1 / math.sqrt(2)
+    assert abs(got[0] - s) < 1e-6 and abs(got[1] - s) < 1e-6
+    assert np.max(np.abs(got[2:])) < 1e-7
+
+
+@pytest.mark.parametrize("kind", ["empty", "sqrtx4", "cz2"])
+def test_identity_circuits(kind):
+    net = circuit_to_network(identity_circuit(6, kind))
+    tree = greedy_tree(net, seed=1)
+    xs = all_bitstrings(6)
+    plan = qxtn.Plan(net, tree, [], max_bitstrings=64)
+    got = gpu_amplitudes(plan, xs)
+    want = np.zeros(64)
+    want[0] = 1
+    assert np.max(np.abs(got - want)) < 1e-6
+
+
+def test_mirror_circuit_30_qubits_sliced():
+    circ = mirror_circuit(5, 6, 6, 23)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=3)
+    sl = tree_trimming(net, tree, 6, seed=3)
+    xs = np.concatenate([[0], random_bitstrings(30, 7, 7)]).astype(np.uint64)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=8)
+    got = gpu_amplitudes(plan, xs)
+    assert abs(got[0] - 1) < 1e-5
+    assert np.max(np.abs(got[1:])) < 1e-5
+
+
+@pytest.mark.parametrize("slice_id", [0, 777])
+def test_c2_one_slice_against_oracle(slice_id):
+    w = configs.get("c2")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs))
+    got = gpu_amplitudes(plan, xs, (slice_id, slice_id + 1))
+    pick = np.arange(0, len(xs), 16)
+    want = oracle.slice_values(net, tree, xs[pick[0]], sl, [slice_id])
+    want = np.array([oracle.contract_slice(net, tree, xs[i], sl, slice_id) for i in pick])
+    assert rms_err(got[pick], want) < TOL_C64
+
+
+def test_errors_leave_plan_usable():
+    w = configs.get("c1")
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings(8)
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=8)
+    x = torch.zeros(9, dtype=torch.int64, device="cuda")
+    amp = torch.zeros((9, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(qxtn.QxError):
+        plan.contract(x, amp)  # B > max_bitstrings
+    with pytest.raises(qxtn.QxError):
+        plan.contract(x[:8], amp, (0, 2))  # slice range beyond 2^0
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_statevector(w.circuit(), xs)
+    assert rms_err(got, want) < TOL_C64

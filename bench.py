@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput of sliced tensor-network amplitude contraction on one MI355X.
+
+One step = one qx_contract call over the whole slice range of the workload
+(every slice of every bitstring), i.e. one pass of the whole hot path:
+gather offsets, per-call sub-trees, then for every block of slices the
+permutes, matrix-core products, small contractions and root inner products,
+and the FP64 slice sum.  Inputs (plan, leaves, bitstrings) are resident on the
+device before the timed region starts.
+
+Prints one JSON line.  ``roofline`` is measured live: every launch in the timed
+region is bracketed by HIP events on the stream it runs on, and the matrix-core
+products' algorithmic flops (8 M N K each) are divided by their summed
+durations.  ``cpu_baseline`` times the FP64 oracle on a bounded sample of the
+same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitudes/s + complex TFLOP/s (% MFMA peak) vs plain c64; p50/p99 latency"
+# MI355X published dense peaks (per GPU)
+PEAKS = {"c64": 157.3e12, "split_bf16": 2516.6e12, "split_fp16": 2516.6e12}
+DTYPES = {"c64": "c64 (fp32 mfma)", "split_bf16": "bf16 hi+lo (fp32 acc)", "split_fp16": "fp16 hi+lo (fp32 acc)"}
+HBM_PEAK = 8.0e12
+
+
+def cpu_baseline(w, tree, sliced, xs, seconds):
+    """Oracle (complex128 tensordot) on slice 0 for as many bitstrings as fit in ``seconds``."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = None
+    net = w.network()
+    vals = []
+    t0 = time.perf_counter()
+    while True:
+        vals.append(oracle.contract_slice(net, tree, xs[len(vals)], sliced, 0))
+        el = time.perf_counter() - t0
+        if el >= seconds or len(vals) == len(xs):
+            break
+    per = el / len(vals)
+    n_slices = 1 << len(sliced)
+    return {
+        "value": 1.0 / (per * n_slices),
+        "unit": "amplitudes/s",
+        "cores": blas_threads or len(os.sched_getaffinity(0)),
+        "kind": "oracle",
+        "sample": f"FP64 oracle (numpy complex128 pairwise tensordot along the same tree) on slice 0 for "
+                  f"{len(vals)} bitstrings in {el:.1f} s, extrapolated x{n_slices} slices",
+        "host_cpus": len(os.sched_getaffinity(0)),
+    }, np.array(vals)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="c64", choices=sorted(PEAKS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not bracket launches with events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(slices shard across GPUs by contiguous ranges, but no multi-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_09894_amd import qxtn
+    from workloads import configs
+
+    w = configs.get(args.workload)
+    tree, sliced, st = w.plan_inputs()
+    xs = w.bitstrings()
+    B = len(xs)
+    net = w.network()
+    torch.cuda.set_device(0)
+    plan = qxtn.Plan(net, tree, sliced, precision=args.precision, max_bitstrings=B)
+    info = plan.info()
+    x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
+    amp = torch.zeros((B, 2), dtype=torch.float64, device="cuda")
+    n_slices = 1 << len(sliced)
+
+    for _ in range(args.warmup):
+        plan.contract(x, amp)
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        plan.set_timing(True)
+        plan.get_timing(reset=True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        plan.contract(x, amp)
+        ends[i].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = plan.get_timing(reset=True) if not args.no_timing else None
+    plan.set_timing(False) if not args.no_timing else None
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    executed = info["flops_block"] * (n_slices >> info["slice_batch_log2"]) + info["flops_call"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[args.precision],
+        "data": "synthetic (seeded random circuit, planner and bitstrings; no external dataset)",
+        "config": {"workload": f"{w.name}: {w.description}", "precision": args.precision,
+                   "qubits": w.n_qubits, "depth": w.depth, "slices": n_slices, "bitstrings": B,
+                   "slice_batch": 1 << info["slice_batch_log2"], "tree_width": st["width"],
+                   "flops_per_slice_amplitude": st["flops_per_slice"]},
+        "complex_tflops": executed / (elapsed / args.steps) / 1e12,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+    }
+    if timing is not None:
+        g = timing["gemm"]
+        ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
+        out["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[args.precision] / 1e12,
+                           "unit": "TFLOP/s", "frac": ach / PEAKS[args.precision], "traffic": None,
+                           "kernel": "k_gemm_f32" if args.precision == "c64" else "k_gemm_split",
+                           "launches_per_step": g["launches"] / args.steps,
+                           "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}
+        out["time_by_class_ms_per_step"] = {k: 1e3 * v["seconds"] / args.steps for k, v in timing.items()}
+        pm = timing["permute"]
+        out["permute_gbs"] = pm["bytes"] / pm["seconds"] / 1e9 if pm["seconds"] > 0 else None
+
+    # accuracy on slice 0 and the CPU baseline share the oracle sample
+    if not args.no_cpu_baseline:
+        cb, ref = cpu_baseline(w, tree, sliced, xs, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        k = len(ref)
+        a0 = torch.zeros((k, 2), dtype=torch.float64, device="cuda")
+        plan.contract(x[:k], a0, (0, 1))
+        torch.cuda.synchronize()
+        got = a0.cpu().numpy()
+        got = got[:, 0] + 1j * got[:, 1]
+        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+        out["error_vs_oracle"] = {"slice": 0, "bitstrings": k,
+                                  "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

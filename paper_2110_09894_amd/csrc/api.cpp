@@ -435,6 +435,7 @@ qx_status qx_permute_c64(const void* d_in, void* d_out, int32_t rank, const int3
   a.n_items = (int)items;
   a.in_item = a.out_item = (int64_t)1 << rank;
   for (int i = 0; i < rank; ++i) a.in_pos[i] = in_pos[i];
+  permute_setup(a);
   HIP_TRY(launch_permute(a, (hipStream_t)stream));
   return QX_OK;
 }

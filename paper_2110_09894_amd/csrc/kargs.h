@@ -60,12 +60,18 @@ struct DotArgs {
 };
 
 // Bit permutation: out[item][o] = in[item][sum_i bit_i(o) << in_pos[i]]
+// The host splits the bits into a tile (the output's lowest bits plus the bits
+// at the input's lowest positions, at most 10) and outer bits.
 struct PermArgs {
   const QxCplx *in;
   QxCplx *out;
   int64_t in_item, out_item;
   int32_t rank, n_items;
   int32_t in_pos[QX_MAX_BITS];
+  int32_t nt, n_outer;                  // tile bits, outer bits
+  int32_t tl[10];                       // tile bits (output-bit indices), ascending
+  int32_t ll[10];                       // tile-bit slots in ascending input position
+  int64_t outer_in[QX_MAX_BITS], outer_out[QX_MAX_BITS];  // strides of outer bit i
 };
 
 // Sum over the slices of one block, FP64, ascending slice order:

@@ -318,67 +318,47 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// Index permutation.  A work-group moves one tile whose bits are the output's
-// lowest TB bits together with the bits that are the input's lowest TB bits,
-// so it reads runs contiguous in the input and writes runs contiguous in the
-// output, transposing through LDS.  The remaining bits select the tile.
+// Index permutation.  A tile is the set of elements that differ only in the
+// output's lowest bits and the bits at the input's lowest positions, so a tile
+// is read in runs contiguous in the input and written in runs contiguous in
+// the output, transposing through LDS.  The outer bits select the tile.  Each
+// work-group builds its offset tables once and then walks many tiles.
 // ---------------------------------------------------------------------------
 constexpr int PERM_TB = 5;
 __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
   __shared__ QxCplx buf[1 << (2 * PERM_TB)];
   __shared__ long long tin[1 << (2 * PERM_TB)];   // load order v -> input offset inside tile
-  __shared__ short tlu[1 << (2 * PERM_TB)]; // load order v -> LDS slot
+  __shared__ short tlu[1 << (2 * PERM_TB)];       // load order v -> LDS slot
   __shared__ long long tout[1 << (2 * PERM_TB)];  // LDS slot u -> output offset inside tile
-  __shared__ int tl[2 * PERM_TB];   // tile bits (output-bit indices), ascending
-  __shared__ int ll[2 * PERM_TB];   // tile-bit slots sorted by input position
-  __shared__ int s_nt;
-  __shared__ unsigned long long s_tmask;
-  const int r = p.rank;
-  const int tb = r < PERM_TB ? r : PERM_TB;
-  if (threadIdx.x == 0) {
-    // tile = output bits 0..tb-1 plus the output bits found at input positions 0..tb-1
-    int nt = 0;
-    unsigned long long tmask = 0;
-    for (int i = 0; i < r; ++i)
-      if (i < tb || p.in_pos[i] < tb) { tl[nt++] = i; tmask |= 1ULL << i; }
-    int nl = 0;
-    for (int pos = 0; pos < r && nl < nt; ++pos)
-      for (int j = 0; j < nt; ++j)
-        if (p.in_pos[tl[j]] == pos) ll[nl++] = j;
-    s_nt = nt;
-    s_tmask = tmask;
-  }
-  __syncthreads();
-  const int nt = s_nt;
-  const unsigned long long tmask = s_tmask;
+  const int nt = p.nt;
   const int tsz = 1 << nt;
   for (int v = threadIdx.x; v < tsz; v += blockDim.x) {
     long long inoff = 0, outoff = 0;
     int u = 0;
     for (int b = 0; b < nt; ++b)
       if ((v >> b) & 1) {
-        inoff += 1LL << p.in_pos[tl[ll[b]]];
-        u |= 1 << ll[b];
-        outoff += 1LL << tl[b];
+        inoff += 1LL << p.in_pos[p.tl[p.ll[b]]];
+        u |= 1 << p.ll[b];
+        outoff += 1LL << p.tl[b];
       }
     tin[v] = inoff;
     tlu[v] = (short)u;
     tout[v] = outoff;
   }
-  // tile base from the outer bits
-  int64_t w = blockIdx.x, ibase = 0, obase = 0;
-  for (int i = 0; i < r; ++i)
-    if (!((tmask >> i) & 1)) {
-      if (w & 1) { obase += 1LL << i; ibase += 1LL << p.in_pos[i]; }
-      w >>= 1;
-    }
-  const int64_t item = blockIdx.y;
-  const QxCplx* __restrict__ in = p.in + item * p.in_item + ibase;
-  QxCplx* __restrict__ out = p.out + item * p.out_item + obase;
-  __syncthreads();
-  for (int v = threadIdx.x; v < tsz; v += blockDim.x) buf[tlu[v]] = in[tin[v]];
-  __syncthreads();
-  for (int u = threadIdx.x; u < tsz; u += blockDim.x) out[tout[u]] = buf[u];
+  const int64_t n_tiles = (int64_t)1 << p.n_outer;
+  const int64_t total = n_tiles * p.n_items;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int64_t item = t >> p.n_outer;
+    int64_t w = t & (n_tiles - 1), ibase = item * p.in_item, obase = item * p.out_item;
+    for (int i = 0; w; ++i, w >>= 1)
+      if (w & 1) { ibase += p.outer_in[i]; obase += p.outer_out[i]; }
+    __syncthreads();  // tables ready / previous tile's LDS reads done
+    const QxCplx* __restrict__ in = p.in + ibase;
+    for (int v = threadIdx.x; v < tsz; v += blockDim.x) buf[tlu[v]] = in[tin[v]];
+    __syncthreads();
+    QxCplx* __restrict__ out = p.out + obase;
+    for (int u = threadIdx.x; u < tsz; u += blockDim.x) out[tout[u]] = buf[u];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -451,13 +431,32 @@ hipError_t launch_dot(const DotArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+void permute_setup(PermArgs& a) {
+  const int r = a.rank;
+  const int tb = r < PERM_TB ? r : PERM_TB;
+  int nt = 0, no = 0;
+  for (int i = 0; i < r; ++i) {
+    if (i < tb || a.in_pos[i] < tb) {
+      a.tl[nt++] = i;
+    } else {
+      a.outer_in[no] = 1LL << a.in_pos[i];
+      a.outer_out[no] = 1LL << i;
+      ++no;
+    }
+  }
+  int nl = 0;
+  for (int pos = 0; pos < r && nl < nt; ++pos)
+    for (int j = 0; j < nt; ++j)
+      if (a.in_pos[a.tl[j]] == pos) a.ll[nl++] = j;
+  a.nt = nt;
+  a.n_outer = no;
+}
+
 hipError_t launch_permute(const PermArgs& a, hipStream_t s) {
-  const int tb = a.rank < PERM_TB ? a.rank : PERM_TB;
-  int nt = 0;
-  for (int i = 0; i < a.rank; ++i)
-    if (i < tb || a.in_pos[i] < tb) ++nt;
-  dim3 grid((unsigned)(1LL << (a.rank - nt)), (unsigned)a.n_items);
-  hipLaunchKernelGGL(k_permute, grid, dim3(256), 0, s, a);
+  const int64_t total = ((int64_t)1 << a.n_outer) * a.n_items;
+  const int64_t grid = total < 4096 ? total : 4096;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -27,9 +27,12 @@
 //   DOT   a long inner product when M*N <= 4 and K >= 256;
 //   SIMT  otherwise (any layout, one thread per output element).
 #include "plan.h"
+#include "kernels.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -183,6 +186,7 @@ struct Compiler {
     op.perm.in_item = src.batched ? src.elems() : 0;
     op.perm.out_item = src.batched ? dst.elems() : 0;
     for (size_t i = 0; i < dst.lay.size(); ++i) op.perm.in_pos[i] = pos_in(src, dst.lay[i]);
+    permute_setup(op.perm);
     const double items = src.batched ? pc.max_b : 1;
     op.bytes = 16.0 * (double)src.elems() * items;
     ops.push_back(op);
@@ -651,6 +655,24 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
     arena = std::max(arena, cand + sz);
   }
   pc.arena_bytes = arena;
+  if (getenv("QX_DUMP_PLAN")) {
+    static const char* kn[] = {"SIMT", "GEMM", "DOT", "PERM"};
+    for (size_t i = 0; i < pc.ops.size(); ++i) {
+      const Op& o = pc.ops[i];
+      if (o.phase != PH_BLOCK && o.kind != OP_PERM && o.kind != OP_GEMM) continue;
+      fprintf(stderr, "op %zu ph %d %s in %d(%zu b%d) %d out %d(%zu b%d) flops %.3g bytes %.3g", i, o.phase,
+              kn[o.kind], o.in_a, pc.tensors[o.in_a].lay.size(), (int)pc.tensors[o.in_a].batched, o.in_b,
+              o.out, pc.tensors[o.out].lay.size(), (int)pc.tensors[o.out].batched, o.flops, o.bytes);
+      if (o.kind == OP_GEMM)
+        fprintf(stderr, " M %lld N %lld K %lld nh %d akc %d bkc %d", (long long)o.gemm.M, (long long)o.gemm.N,
+                (long long)o.gemm.K, o.gemm.nh, (int)(o.gemm.a_ks == 1), (int)(o.gemm.b_ks == 1));
+      if (o.kind == OP_PERM) {
+        fprintf(stderr, " in_pos");
+        for (int j = 0; j < o.perm.rank; ++j) fprintf(stderr, " %d", o.perm.in_pos[j]);
+      }
+      fprintf(stderr, "\n");
+    }
+  }
   // root read-out
   {
     const Tensor& r = pc.tensors[pc.root];

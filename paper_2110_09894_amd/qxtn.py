@@ -29,7 +29,9 @@ QX_SPLIT_FP16 = 2
 PRECISIONS = {"c64": QX_C64, "split_bf16": QX_SPLIT_BF16, "split_fp16": QX_SPLIT_FP16}
 
 EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_contract", "qx_plan_destroy", "qx_last_error",
-            "qx_permute_c64", "qx_cgemm"]
+            "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm"]
+
+OPCLASSES = ["gemm", "simt", "dot", "permute", "slice_sum", "gather"]
 
 
 class QxError(RuntimeError):
@@ -63,6 +65,10 @@ class PlanInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class _OpTiming(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 _lib = None
 
 
@@ -83,6 +89,10 @@ def lib():
         L.qx_plan_destroy.argtypes = [C.c_void_p]
         L.qx_last_error.restype = C.c_char_p
         L.qx_last_error.argtypes = []
+        L.qx_plan_set_timing.restype = C.c_int
+        L.qx_plan_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.qx_plan_get_timing.restype = C.c_int
+        L.qx_plan_get_timing.argtypes = [C.c_void_p, C.POINTER(_OpTiming), C.c_int32]
         L.qx_permute_c64.restype = C.c_int
         L.qx_permute_c64.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int64, C.c_void_p]
         L.qx_cgemm.restype = C.c_int
@@ -156,6 +166,15 @@ class Plan:
         B = int(bitstrings.shape[0])
         _check(lib().qx_contract(self.handle, C.c_void_p(bitstrings.data_ptr()), B, int(lo), int(hi),
                                  C.c_void_p(amplitudes.data_ptr()), _stream_handle(stream)))
+
+    def set_timing(self, enable: bool):
+        _check(lib().qx_plan_set_timing(self.handle, int(bool(enable))))
+
+    def get_timing(self, reset=False) -> dict:
+        arr = (_OpTiming * len(OPCLASSES))()
+        _check(lib().qx_plan_get_timing(self.handle, arr, int(bool(reset))))
+        return {name: {"launches": arr[i].launches, "seconds": arr[i].seconds, "flops": arr[i].flops,
+                       "bytes": arr[i].bytes} for i, name in enumerate(OPCLASSES)}
 
     def destroy(self):
         if getattr(self, "handle", None) is not None:

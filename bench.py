@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "amplitudes/s + complex TFLOP/s (% MFMA peak) vs plain c64; p50/p99 latency"
 # MI355X published dense peaks (per GPU)
 PEAKS = {"c64": 157.3e12, "split_bf16": 2516.6e12, "split_fp16": 2516.6e12}
-DTYPES = {"c64": "c64 (fp32 mfma)", "split_bf16": "bf16 hi+lo (fp32 acc)", "split_fp16": "fp16 hi+lo (fp32 acc)"}
+DTYPES = {"c64": "c64 (fp32 mfma)", "split_bf16": "bf16 hi+lo x3 (fp32 acc)", "split_fp16": "fp16 hi+lo x3 (fp32 acc)"}
 HBM_PEAK = 8.0e12
 
 
@@ -145,6 +145,7 @@ def main():
         out["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[args.precision] / 1e12,
                            "unit": "TFLOP/s", "frac": ach / PEAKS[args.precision], "traffic": None,
                            "kernel": "k_gemm_f32" if args.precision == "c64" else "k_gemm_split",
+                           "mfma_util": ach * (1 if args.precision == "c64" else 3) / PEAKS[args.precision],
                            "launches_per_step": g["launches"] / args.steps,
                            "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}
         out["time_by_class_ms_per_step"] = {k: 1e3 * v["seconds"] / args.steps for k, v in timing.items()}

@@ -158,7 +158,8 @@ typedef enum {
   QX_OPCLASS_PERMUTE = 3,   /* index permutations */
   QX_OPCLASS_SLICESUM = 4,  /* FP64 sum over slices */
   QX_OPCLASS_GATHER = 5,    /* per-bitstring gather offsets */
-  QX_N_OPCLASS = 6
+  QX_OPCLASS_SCALE = 6,     /* operand magnitude reductions for FP16 scaling */
+  QX_N_OPCLASS = 7
 } qx_opclass;
 
 typedef struct {

@@ -44,12 +44,17 @@ struct qx_plan {
   QxCplx* d_leaves = nullptr;
   char* d_arena = nullptr;
   int64_t* d_gather = nullptr;
+  float* d_misc = nullptr;            // FP16 operand scales, absmax partials, absmax ticket
   int64_t device_bytes = 0;
 };
 
+static int64_t misc_bytes(const PlanCore& pc) {
+  return ((int64_t)pc.n_scale_slots + ABSMAX_PARTIALS + 64) * 4;
+}
+
 static int64_t plan_device_bytes(const PlanCore& pc) {
   return ((pc.leaf_pool_elems * 8 + 255) / 256) * 256 + pc.arena_bytes +
-         (int64_t)pc.gathers.size() * pc.max_b * 8;
+         (int64_t)pc.gathers.size() * pc.max_b * 8 + misc_bytes(pc);
 }
 
 static QxCplx* tensor_ptr(qx_plan* p, int tid) {
@@ -61,11 +66,13 @@ static const int64_t* gather_ptr(qx_plan* p, int g) {
   return g < 0 ? nullptr : p->d_gather + (int64_t)g * p->pc.max_b;
 }
 
+static float* scale_ptr(qx_plan* p, int slot) { return slot < 0 ? nullptr : p->d_misc + 64 + ABSMAX_PARTIALS + slot; }
+
 static void resolve_pointers(qx_plan* p) {
   for (Op& op : p->pc.ops) {
     QxCplx* a = op.in_a >= 0 ? tensor_ptr(p, op.in_a) : nullptr;
     QxCplx* b = op.in_b >= 0 ? tensor_ptr(p, op.in_b) : nullptr;
-    QxCplx* c = tensor_ptr(p, op.out);
+    QxCplx* c = op.out >= 0 ? tensor_ptr(p, op.out) : nullptr;
     switch (op.kind) {
       case OP_SIMT:
         op.simt.a = a; op.simt.b = b; op.simt.c = c;
@@ -76,6 +83,14 @@ static void resolve_pointers(qx_plan* p) {
         op.gemm.a = a; op.gemm.b = b; op.gemm.c = c;
         op.gemm.a_gather = gather_ptr(p, op.gather_a);
         op.gemm.b_gather = gather_ptr(p, op.gather_b);
+        op.gemm.a_scale = scale_ptr(p, op.scale_slot);
+        op.gemm.b_scale = op.scale_slot >= 0 ? scale_ptr(p, op.scale_slot + 1) : nullptr;
+        break;
+      case OP_ABSMAX:
+        op.absmax.x = a;
+        op.absmax.ticket = reinterpret_cast<unsigned int*>(p->d_misc);
+        op.absmax.partial = p->d_misc + 64;
+        op.absmax.scale = scale_ptr(p, op.scale_slot);
         break;
       case OP_DOT:
         op.dot.a = a; op.dot.b = b; op.dot.c = c;
@@ -118,6 +133,7 @@ static int op_class(int kind) {
     case OP_GEMM: return QX_OPCLASS_GEMM;
     case OP_DOT: return QX_OPCLASS_DOT;
     case OP_PERM: return QX_OPCLASS_PERMUTE;
+    case OP_ABSMAX: return QX_OPCLASS_SCALE;
     default: return QX_OPCLASS_SIMT;
   }
 }
@@ -130,7 +146,7 @@ static int64_t fix_offset(const std::vector<FixTerm>& fx, int64_t sbase) {
 }
 
 static qx_status run_op(qx_plan* p, const Op& op, int B, int64_t sbase, hipStream_t s) {
-  const bool outb = p->pc.tensors[op.out].batched;
+  const bool outb = op.out >= 0 ? p->pc.tensors[op.out].batched : false;
   const int64_t fa = fix_offset(op.fix_a, sbase), fb = fix_offset(op.fix_b, sbase);
   const double scale = outb ? (double)B / p->pc.max_b : 1.0;
   hipError_t e = timed(p, op_class(op.kind), op.flops * scale, op.bytes * scale, s, [&]() -> hipError_t {
@@ -152,6 +168,12 @@ static qx_status run_op(qx_plan* p, const Op& op, int B, int64_t sbase, hipStrea
       d.a += fa; d.b += fb;
       if (outb) d.n_items = B;
       return launch_dot(d, s);
+    }
+    case OP_ABSMAX: {
+      AbsmaxArgs m = op.absmax;
+      const Tensor& t = p->pc.tensors[op.in_a];
+      m.n = t.elems() * (t.batched ? B : 1);
+      return launch_absmax(m, s);
     }
     case OP_PERM: {
       PermArgs q = op.perm;
@@ -255,6 +277,10 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(leaves): ") + hipGetErrorString(e));
     if ((e = hipMalloc((void**)&p->d_arena, std::max<int64_t>(256, p->pc.arena_bytes))) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(arena): ") + hipGetErrorString(e));
+    if ((e = hipMalloc((void**)&p->d_misc, misc_bytes(p->pc))) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMalloc(misc): ") + hipGetErrorString(e));
+    if ((e = hipMemsetAsync(p->d_misc, 0, misc_bytes(p->pc), s)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMemsetAsync(misc): ") + hipGetErrorString(e));
     const int64_t gb = std::max<int64_t>(256, (int64_t)p->pc.gathers.size() * p->pc.max_b * 8);
     if ((e = hipMalloc((void**)&p->d_gather, gb)) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(gather): ") + hipGetErrorString(e));
@@ -409,6 +435,7 @@ void qx_plan_destroy(qx_plan* p) {
     if (p->d_leaves) hipFree(p->d_leaves);
     if (p->d_arena) hipFree(p->d_arena);
     if (p->d_gather) hipFree(p->d_gather);
+    if (p->d_misc) hipFree(p->d_misc);
     hipSetDevice(cur);
   }
   delete p;

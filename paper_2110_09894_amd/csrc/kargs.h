@@ -43,7 +43,7 @@ struct GemmArgs {
   const int64_t *a_gather, *b_gather;
   int32_t n_items, nh;                   // nh = number of shared-slice bits
   int32_t vec_a, vec_b;                  // 16-byte vector loads allowed along k (alignment)
-  int32_t pad_;
+  const float *a_scale, *b_scale;        // split FP16: power-of-two operand scales (null = 1)
   int64_t a_hs[QX_MAX_HBITS], b_hs[QX_MAX_HBITS], c_hs[QX_MAX_HBITS];
 };
 
@@ -84,6 +84,18 @@ struct SliceSumArgs {
   int32_t n_items, n_sbits;
   int32_t s_lo, s_hi;
   int64_t s_stride[QX_MAX_SBITS];
+};
+
+// Largest magnitude of a tensor -> power-of-two scale for FP16 operands:
+//   scale[0] = 2^(14 - e) with max |re|, |im| < 2^e   (1 if the tensor is zero)
+// Work-groups write partial maxima; the last one to finish (ticket counter)
+// reduces them, writes the scale and resets the counter for the next launch.
+struct AbsmaxArgs {
+  const QxCplx *x;
+  int64_t n;                            // complex elements
+  float *partial;                       // [gridDim.x]
+  unsigned int *ticket;                 // zero before the first launch; left zero after each
+  float *scale;
 };
 
 // Per-bitstring gather offsets: out[item] = sum_j bit_{q_j}(x[item]) * stride_j

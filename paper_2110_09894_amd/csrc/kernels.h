@@ -14,5 +14,7 @@ void permute_setup(PermArgs& a);  // fills the tile / outer-bit fields from rank
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s);  // grid <= 1024 work-groups
+constexpr int ABSMAX_PARTIALS = 1024;
 
 }  // namespace qx

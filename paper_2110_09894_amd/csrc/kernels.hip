@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include "kargs.h"
 #include "kernels.h"
+#include "qxtn.h"
 
 namespace qx {
 
@@ -63,6 +64,83 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Operand tile loader shared by the matrix-product kernels.  A tile is ROWS
+// rows x 16 k of complex64; every chunk is 8 consecutive k of one row.  For a
+// k-contiguous operand a thread reads its chunk with 16-byte loads; for a
+// row-contiguous operand consecutive lanes take consecutive rows, so every
+// 8-byte load instruction is coalesced across the wave.
+// ---------------------------------------------------------------------------
+template <int ROWS, bool KC>
+struct TileLoader {
+  static constexpr int BK = 16;
+  static constexpr int CH = ROWS * (BK / 8);
+  static constexpr int P = (CH + 255) / 256;
+  __device__ static inline void row_kg(int c, int& r, int& kg) {
+    r = KC ? c / (BK / 8) : c % ROWS;
+    kg = KC ? c % (BK / 8) : c / ROWS;
+  }
+  __device__ static inline void load(const QxCplx* __restrict__ X, int64_t rows, int64_t K, int64_t ld_r,
+                                     int64_t ld_k, int64_t r0, int64_t k0, bool vec, int tid,
+                                     QxCplx (&reg)[P][8]) {
+#pragma unroll
+    for (int ps = 0; ps < P; ++ps) {
+      const int c = tid + ps * 256;
+      if (c >= CH) continue;
+      int r, kg;
+      row_kg(c, r, kg);
+      const int64_t row = r0 + r, kb = k0 + kg * 8;
+      if (KC) {
+        const QxCplx* src = X + row * ld_r + kb;
+        if (vec && row < rows && kb + 8 <= K) {
+#pragma unroll
+          for (int j = 0; j < 8; j += 2) {
+            v4f v = *(const v4f*)(src + j);
+            reg[ps][j] = {v[0], v[1]};
+            reg[ps][j + 1] = {v[2], v[3]};
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) reg[ps][j] = (row < rows && kb + j < K) ? src[j] : QxCplx{0.f, 0.f};
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          reg[ps][j] = (row < rows && kb + j < K) ? X[(kb + j) * ld_k + row] : QxCplx{0.f, 0.f};
+      }
+    }
+  }
+};
+
+// Work-group -> (batch item, hyper index, tile) with an XCD-aware order:
+// hardware deals work-groups round-robin over the 8 XCDs, so each XCD gets a
+// contiguous run of logical tiles and neighbours share its L2.
+struct TileCoord {
+  int item;
+  int64_t tm, tn, aoff, boff, coff;
+};
+__device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
+  const int64_t tiles_n = (p.N + BN - 1) / BN;
+  const int64_t tiles = ((p.M + BM - 1) / BM) * tiles_n;
+  const int64_t nwg = (int64_t)gridDim.x;
+  int64_t w = blockIdx.x;
+  const int64_t per = nwg / 8;
+  if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
+  const int64_t z = w / tiles, t = w % tiles;
+  TileCoord tc;
+  tc.tm = t / tiles_n;
+  tc.tn = t % tiles_n;
+  tc.item = (int)(z >> p.nh);
+  const int64_t h = z & ((1LL << p.nh) - 1);
+  tc.aoff = (int64_t)tc.item * p.a_item + (p.a_gather ? p.a_gather[tc.item] : 0);
+  tc.boff = (int64_t)tc.item * p.b_item + (p.b_gather ? p.b_gather[tc.item] : 0);
+  tc.coff = (int64_t)tc.item * p.c_item;
+#pragma unroll
+  for (int i = 0; i < QX_MAX_HBITS; ++i)
+    if (i < p.nh && ((h >> i) & 1)) { tc.aoff += p.a_hs[i]; tc.boff += p.b_hs[i]; tc.coff += p.c_hs[i]; }
+  return tc;
+}
+
+// ---------------------------------------------------------------------------
 // Complex GEMM on FP32 matrix cores (v_mfma_f32_32x32x2_f32).
 // Work-group tile BM x BN, 4 waves in a 2x2 grid, K tile of 16 complex values.
 // Both operand tiles are staged in LDS as [row][k] (k contiguous), so each lane
@@ -77,102 +155,30 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   constexpr int PITCH = BK + 2;            // complex per LDS row (+16 B against bank conflicts)
   constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int CHA = BM * (BK / 8), CHB = BN * (BK / 8);  // 8-element chunks per tile
-  constexpr int PA = (CHA + 255) / 256, PB = (CHB + 255) / 256;
+  using LA = TileLoader<BM, A_KC>;
+  using LB = TileLoader<BN, B_KC>;
   __shared__ __attribute__((aligned(16))) QxCplx As[2][BM * PITCH];
   __shared__ __attribute__((aligned(16))) QxCplx Bs[2][BN * PITCH];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t tiles_m = (p.M + BM - 1) / BM, tiles_n = (p.N + BN - 1) / BN;
-  const int64_t tiles = tiles_m * tiles_n;
-  const int64_t nwg = (int64_t)gridDim.x;
-  // XCD-aware order: hardware deals work-groups round-robin over 8 XCDs; give
-  // each XCD a contiguous run of logical tiles so neighbours share its L2.
-  int64_t w = blockIdx.x;
-  const int64_t per = nwg / 8;
-  if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
-  const int64_t z = w / tiles, t = w % tiles;
-  const int64_t tm = t / tiles_n, tn = t % tiles_n;
-  const int item = (int)(z >> p.nh);
-  const int64_t h = z & ((1LL << p.nh) - 1);
-  int64_t aoff = (int64_t)item * p.a_item + (p.a_gather ? p.a_gather[item] : 0);
-  int64_t boff = (int64_t)item * p.b_item + (p.b_gather ? p.b_gather[item] : 0);
-  int64_t coff = (int64_t)item * p.c_item;
-#pragma unroll
-  for (int i = 0; i < QX_MAX_HBITS; ++i)
-    if (i < p.nh && ((h >> i) & 1)) { aoff += p.a_hs[i]; boff += p.b_hs[i]; coff += p.c_hs[i]; }
-  const QxCplx* __restrict__ A = p.a + aoff;
-  const QxCplx* __restrict__ B = p.b + boff;
-  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const TileCoord tc = tile_coord(p, BM, BN);
+  const QxCplx* __restrict__ A = p.a + tc.aoff;
+  const QxCplx* __restrict__ B = p.b + tc.boff;
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
 
-  QxCplx ra[PA][8], rb[PB][8];
-
+  QxCplx ra[LA::P][8], rb[LB::P][8];
   auto load_tiles = [&](int64_t k0) {
-#pragma unroll
-    for (int ps = 0; ps < PA; ++ps) {
-      const int c = tid + ps * 256;
-      if (c < CHA) {
-        const int r = A_KC ? c / (BK / 8) : c % BM;
-        const int kg = A_KC ? c % (BK / 8) : c / BM;
-        const int64_t m = m0 + r, kb = k0 + kg * 8;
-        if (A_KC) {
-          const QxCplx* src = A + m * p.a_ms + kb;
-          if (p.vec_a && m < p.M && kb + 8 <= p.K) {
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-              v4f v = *(const v4f*)(src + j);
-              ra[ps][j] = {v[0], v[1]};
-              ra[ps][j + 1] = {v[2], v[3]};
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-              ra[ps][j] = (m < p.M && kb + j < p.K) ? src[j] : QxCplx{0.f, 0.f};
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            ra[ps][j] = (m < p.M && kb + j < p.K) ? A[(kb + j) * p.a_ks + m] : QxCplx{0.f, 0.f};
-        }
-      }
-    }
-#pragma unroll
-    for (int ps = 0; ps < PB; ++ps) {
-      const int c = tid + ps * 256;
-      if (c < CHB) {
-        const int r = B_KC ? c / (BK / 8) : c % BN;
-        const int kg = B_KC ? c % (BK / 8) : c / BN;
-        const int64_t n = n0 + r, kb = k0 + kg * 8;
-        if (B_KC) {
-          const QxCplx* src = B + n * p.b_ns + kb;
-          if (p.vec_b && n < p.N && kb + 8 <= p.K) {
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-              v4f v = *(const v4f*)(src + j);
-              rb[ps][j] = {v[0], v[1]};
-              rb[ps][j + 1] = {v[2], v[3]};
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-              rb[ps][j] = (n < p.N && kb + j < p.K) ? src[j] : QxCplx{0.f, 0.f};
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            rb[ps][j] = (n < p.N && kb + j < p.K) ? B[(kb + j) * p.b_ks + n] : QxCplx{0.f, 0.f};
-        }
-      }
-    }
+    LA::load(A, p.M, p.K, p.a_ms, p.a_ks, m0, k0, p.vec_a, tid, ra);
+    LB::load(B, p.N, p.K, p.b_ns, p.b_ks, n0, k0, p.vec_b, tid, rb);
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int ps = 0; ps < PA; ++ps) {
+    for (int ps = 0; ps < LA::P; ++ps) {
       const int c = tid + ps * 256;
-      if (c < CHA) {
-        const int r = A_KC ? c / (BK / 8) : c % BM;
-        const int kg = A_KC ? c % (BK / 8) : c / BM;
+      if (c < LA::CH) {
+        int r, kg;
+        LA::row_kg(c, r, kg);
         QxCplx* dst = &As[buf][r * PITCH + kg * 8];
 #pragma unroll
         for (int j = 0; j < 8; j += 2)
@@ -180,11 +186,11 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
       }
     }
 #pragma unroll
-    for (int ps = 0; ps < PB; ++ps) {
+    for (int ps = 0; ps < LB::P; ++ps) {
       const int c = tid + ps * 256;
-      if (c < CHB) {
-        const int r = B_KC ? c / (BK / 8) : c % BN;
-        const int kg = B_KC ? c % (BK / 8) : c / BN;
+      if (c < LB::CH) {
+        int r, kg;
+        LB::row_kg(c, r, kg);
         QxCplx* dst = &Bs[buf][r * PITCH + kg * 8];
 #pragma unroll
         for (int j = 0; j < 8; j += 2)
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
     __syncthreads();
   }
 
-  QxCplx* __restrict__ C = p.c + coff;
+  QxCplx* __restrict__ C = p.c + tc.coff;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -268,6 +274,204 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
         const int64_t m = m0 + wm * WM + a * 32 + 8 * (i / 4) + 4 * g + (i % 4);
         const int64_t n = n0 + wn * WN + b * 32 + lrow;
         if (m < p.M && n < p.N) C[m * p.c_ms + n] = QxCplx{cr[a][b][i], ci[a][b][i]};
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Split-precision complex GEMM on BF16 / FP16 matrix cores.
+// Each FP32 value x is split into hi = round(x) and lo = round(x - hi) in the
+// 16-bit format when the tile is staged in LDS, and
+//   A B ~= Ah Bh + Ah Bl + Al Bh
+// is accumulated in FP32 (v_mfma_f32_32x32x16_{bf16,f16}).  For FP16 both
+// operands are first scaled by powers of two that bring their largest
+// magnitude near 2^14 (exact, undone in the epilogue).  LDS holds four planes
+// per operand (re hi, re lo, im hi, im lo) as [row][k]; lane group g = l/32
+// supplies k in [8g, 8g+8) of one 16-wide step for both operands.
+// ---------------------------------------------------------------------------
+template <int PREC> struct Half16;
+template <> struct Half16<QX_SPLIT_BF16> {
+  typedef __bf16 T;
+  typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+  __device__ static inline T cvt(float x) { return (T)x; }
+  __device__ static inline v16f mfma(V8 a, V8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Half16<QX_SPLIT_FP16> {
+  typedef _Float16 T;
+  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+  __device__ static inline T cvt(float x) { return (T)x; }
+  __device__ static inline v16f mfma(V8 a, V8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int BM, int BN, bool A_KC, bool B_KC, int PREC>
+__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
+  using H = Half16<PREC>;
+  using T = typename H::T;
+  using V8 = typename H::V8;
+  constexpr int BK = 16;
+  constexpr int P16 = BK + 8;              // 16-bit elements per LDS row (+16 B pad)
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  using LA = TileLoader<BM, A_KC>;
+  using LB = TileLoader<BN, B_KC>;
+  __shared__ __attribute__((aligned(16))) T As[2][4][BM * P16];
+  __shared__ __attribute__((aligned(16))) T Bs[2][4][BN * P16];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const TileCoord tc = tile_coord(p, BM, BN);
+  const QxCplx* __restrict__ A = p.a + tc.aoff;
+  const QxCplx* __restrict__ B = p.b + tc.boff;
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const float sa = p.a_scale ? p.a_scale[0] : 1.f;
+  const float sb = p.b_scale ? p.b_scale[0] : 1.f;
+
+  QxCplx ra[LA::P][8], rb[LB::P][8];
+  auto load_tiles = [&](int64_t k0) {
+    LA::load(A, p.M, p.K, p.a_ms, p.a_ks, m0, k0, p.vec_a, tid, ra);
+    LB::load(B, p.N, p.K, p.b_ns, p.b_ks, n0, k0, p.vec_b, tid, rb);
+  };
+  // split 8 complex values into the four planes and store 16 bytes per plane
+  auto split_store = [&](T* p0, T* p1, T* p2, T* p3, const QxCplx (&v)[8], float sc) {
+    V8 rh, rl, ih, il;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float xr = v[j].x * sc, xi = v[j].y * sc;
+      const T hr = H::cvt(xr), hi = H::cvt(xi);
+      rh[j] = hr;
+      rl[j] = H::cvt(xr - (float)hr);
+      ih[j] = hi;
+      il[j] = H::cvt(xi - (float)hi);
+    }
+    *(V8*)p0 = rh;
+    *(V8*)p1 = rl;
+    *(V8*)p2 = ih;
+    *(V8*)p3 = il;
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int ps = 0; ps < LA::P; ++ps) {
+      const int c = tid + ps * 256;
+      if (c < LA::CH) {
+        int r, kg;
+        LA::row_kg(c, r, kg);
+        const int o = r * P16 + kg * 8;
+        split_store(&As[buf][0][o], &As[buf][1][o], &As[buf][2][o], &As[buf][3][o], ra[ps], sa);
+      }
+    }
+#pragma unroll
+    for (int ps = 0; ps < LB::P; ++ps) {
+      const int c = tid + ps * 256;
+      if (c < LB::CH) {
+        int r, kg;
+        LB::row_kg(c, r, kg);
+        const int o = r * P16 + kg * 8;
+        split_store(&Bs[buf][0][o], &Bs[buf][1][o], &Bs[buf][2][o], &Bs[buf][3][o], rb[ps], sb);
+      }
+    }
+  };
+
+  v16f cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      cr[a][b] = v16f{0};
+      ci[a][b] = v16f{0};
+    }
+
+  const int64_t nk = (p.K + BK - 1) / BK;
+  load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
+  const int lrow = lane & 31, g = lane >> 5;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+    V8 arh[FM], arl[FM], aih[FM], ail[FM], naih[FM], nail[FM];
+    V8 brh[FN], brl[FN], bih[FN], bil[FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int o = (wm * WM + a * 32 + lrow) * P16 + g * 8;
+      arh[a] = *(const V8*)&As[buf][0][o];
+      arl[a] = *(const V8*)&As[buf][1][o];
+      aih[a] = *(const V8*)&As[buf][2][o];
+      ail[a] = *(const V8*)&As[buf][3][o];
+      u4 t0 = *(u4*)&aih[a], t1 = *(u4*)&ail[a];
+      t0 ^= 0x80008000u;  // flip the sign of both 16-bit halves
+      t1 ^= 0x80008000u;
+      naih[a] = *(V8*)&t0;
+      nail[a] = *(V8*)&t1;
+    }
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int o = (wn * WN + b * 32 + lrow) * P16 + g * 8;
+      brh[b] = *(const V8*)&Bs[buf][0][o];
+      brl[b] = *(const V8*)&Bs[buf][1][o];
+      bih[b] = *(const V8*)&Bs[buf][2][o];
+      bil[b] = *(const V8*)&Bs[buf][3][o];
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(arh[a], brh[b], cr[a][b]);
+        ci[a][b] = H::mfma(arh[a], bih[b], ci[a][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(naih[a], bih[b], cr[a][b]);
+        ci[a][b] = H::mfma(aih[a], brh[b], ci[a][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(arh[a], brl[b], cr[a][b]);
+        ci[a][b] = H::mfma(arh[a], bil[b], ci[a][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(arl[a], brh[b], cr[a][b]);
+        ci[a][b] = H::mfma(arl[a], bih[b], ci[a][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(naih[a], bil[b], cr[a][b]);
+        ci[a][b] = H::mfma(aih[a], brl[b], ci[a][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        cr[a][b] = H::mfma(nail[a], bih[b], cr[a][b]);
+        ci[a][b] = H::mfma(ail[a], brh[b], ci[a][b]);
+      }
+    if (kt + 1 < nk) store_tiles(buf ^ 1);
+    __syncthreads();
+  }
+
+  const float unscale = 1.f / (sa * sb);
+  QxCplx* __restrict__ C = p.c + tc.coff;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t m = m0 + wm * WM + a * 32 + 8 * (i / 4) + 4 * g + (i % 4);
+        const int64_t n = n0 + wn * WN + b * 32 + lrow;
+        if (m < p.M && n < p.N) C[m * p.c_ms + n] = QxCplx{cr[a][b][i] * unscale, ci[a][b][i] * unscale};
       }
 }
 
@@ -382,6 +586,49 @@ __global__ __launch_bounds__(256) void k_slice_sum(SliceSumArgs p) {
   p.amp[2 * item + 1] += si;
 }
 
+constexpr int ABSMAX_GRID = 1024;
+__global__ __launch_bounds__(256) void k_absmax(AbsmaxArgs p) {
+  __shared__ float red[4];
+  __shared__ int last;
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const QxCplx v = p.x[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    p.partial[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __threadfence();
+    last = atomicAdd(p.ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  float mm = 0.f;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) mm = fmaxf(mm, __ldg(&p.partial[i]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mm = fmaxf(mm, __shfl_xor(mm, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    float sc = 1.f;
+    if (mx > 0.f && mx < 3.0e38f) {
+      int e;
+      frexpf(mx, &e);  // mx < 2^e
+      int k = 14 - e;
+      k = k > 100 ? 100 : (k < -100 ? -100 : k);
+      sc = ldexpf(1.f, k);
+    }
+    p.scale[0] = sc;
+    *p.ticket = 0u;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gather(GatherArgs p) {
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= p.n_items) return;
@@ -402,7 +649,7 @@ hipError_t launch_simt(const SimtArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int PREC>
 static hipError_t launch_gemm_tile(const GemmArgs& a, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
@@ -410,18 +657,30 @@ static hipError_t launch_gemm_tile(const GemmArgs& a, hipStream_t s) {
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool akc = a.a_ks == 1, bkc = a.b_ks == 1;
   dim3 grid((unsigned)nwg), block(256);
-  if (akc && bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, true>), grid, block, 0, s, a);
-  else if (akc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, false>), grid, block, 0, s, a);
-  else if (bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_gemm_f32<BM, BN, false, false>), grid, block, 0, s, a);
+  if (PREC == QX_C64) {
+    if (akc && bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, true>), grid, block, 0, s, a);
+    else if (akc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, false>), grid, block, 0, s, a);
+    else if (bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_gemm_f32<BM, BN, false, false>), grid, block, 0, s, a);
+  } else {
+    constexpr int PR = PREC == QX_C64 ? QX_SPLIT_BF16 : PREC;
+    if (akc && bkc) hipLaunchKernelGGL((k_gemm_split<BM, BN, true, true, PR>), grid, block, 0, s, a);
+    else if (akc) hipLaunchKernelGGL((k_gemm_split<BM, BN, true, false, PR>), grid, block, 0, s, a);
+    else if (bkc) hipLaunchKernelGGL((k_gemm_split<BM, BN, false, true, PR>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_gemm_split<BM, BN, false, false, PR>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmArgs& a, int precision, int tile, hipStream_t s) {
-  (void)precision;
-  switch (tile) {
-    case GEMM_TILE_64x64: return launch_gemm_tile<64, 64>(a, s);
-    default: return launch_gemm_tile<128, 128>(a, s);
+  const bool small = tile == GEMM_TILE_64x64;
+  switch (precision) {
+    case QX_SPLIT_BF16:
+      return small ? launch_gemm_tile<64, 64, QX_SPLIT_BF16>(a, s) : launch_gemm_tile<128, 128, QX_SPLIT_BF16>(a, s);
+    case QX_SPLIT_FP16:
+      return small ? launch_gemm_tile<64, 64, QX_SPLIT_FP16>(a, s) : launch_gemm_tile<128, 128, QX_SPLIT_FP16>(a, s);
+    default:
+      return small ? launch_gemm_tile<64, 64, QX_C64>(a, s) : launch_gemm_tile<128, 128, QX_C64>(a, s);
   }
 }
 
@@ -463,6 +722,13 @@ hipError_t launch_permute(const PermArgs& a, hipStream_t s) {
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n_items + 255) / 256));
   hipLaunchKernelGGL(k_slice_sum, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s) {
+  const int64_t want = (a.n + 255) / 256;
+  const int grid = (int)(want < 1 ? 1 : (want > ABSMAX_GRID ? ABSMAX_GRID : want));
+  hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

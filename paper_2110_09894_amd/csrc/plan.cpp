@@ -382,6 +382,23 @@ struct Compiler {
           g.c_hs[i] = (int64_t)1 << (fA.size() + fB.size() + i);
         }
         op.kind = OP_GEMM;
+        if (pc.precision == QX_SPLIT_FP16) {
+          // operand scales: max magnitude of each operand's stored tensor
+          op.scale_slot = pc.n_scale_slots;
+          pc.n_scale_slots += 2;
+          for (int side = 0; side < 2; ++side) {
+            const int ti = side == 0 ? tA : tB;
+            Op am;
+            am.kind = OP_ABSMAX;
+            am.phase = pc.tensors[ti].phase;
+            am.in_a = ti;
+            am.out = -1;
+            am.scale_slot = op.scale_slot + side;
+            std::memset(&am.absmax, 0, sizeof(am.absmax));
+            am.bytes = 8.0 * (double)pc.tensors[ti].elems() * (pc.tensors[ti].batched ? pc.max_b : 1);
+            ops.push_back(am);
+          }
+        }
         const double flops = 8.0 * (double)g.M * g.N * g.K * std::ldexp(1.0, g.nh) * items;
         op.flops = flops;
         op.tile = (g.M >= 128 && g.N >= 128) ? 0 : 1;
@@ -616,9 +633,11 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
   }
   for (int i = 0; i < (int)pc.ops.size(); ++i) {
     const Op& o = pc.ops[i];
-    Tensor& out = pc.tensors[o.out];
-    out.first_op = i;
-    out.last_op = std::max(out.last_op, i);
+    if (o.out >= 0) {
+      Tensor& out = pc.tensors[o.out];
+      out.first_op = i;
+      out.last_op = std::max(out.last_op, i);
+    }
     for (int in : {o.in_a, o.in_b}) {
       if (in < 0) continue;
       Tensor& ti = pc.tensors[in];
@@ -659,7 +678,7 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
     static const char* kn[] = {"SIMT", "GEMM", "DOT", "PERM"};
     for (size_t i = 0; i < pc.ops.size(); ++i) {
       const Op& o = pc.ops[i];
-      if (o.phase != PH_BLOCK && o.kind != OP_PERM && o.kind != OP_GEMM) continue;
+      if (o.kind == OP_ABSMAX || (o.phase != PH_BLOCK && o.kind != OP_PERM && o.kind != OP_GEMM)) continue;
       fprintf(stderr, "op %zu ph %d %s in %d(%zu b%d) %d out %d(%zu b%d) flops %.3g bytes %.3g", i, o.phase,
               kn[o.kind], o.in_a, pc.tensors[o.in_a].lay.size(), (int)pc.tensors[o.in_a].batched, o.in_b,
               o.out, pc.tensors[o.out].lay.size(), (int)pc.tensors[o.out].batched, o.flops, o.bytes);

@@ -25,7 +25,7 @@
 namespace qx {
 
 enum Phase { PH_CONST = 0, PH_CALL = 1, PH_BLOCK = 2 };
-enum OpKind { OP_SIMT = 0, OP_GEMM = 1, OP_DOT = 2, OP_PERM = 3 };
+enum OpKind { OP_SIMT = 0, OP_GEMM = 1, OP_DOT = 2, OP_PERM = 3, OP_ABSMAX = 4 };
 
 struct Tensor {
   bool is_leaf = false;
@@ -56,6 +56,8 @@ struct Op {
   GemmArgs gemm;
   DotArgs dot;
   PermArgs perm;
+  AbsmaxArgs absmax;
+  int scale_slot = -1;                 // ABSMAX: slot written; GEMM: slot of A (B = slot + 1)
 };
 
 struct GatherDesc {
@@ -88,6 +90,7 @@ struct PlanCore {
   int width = 0;
   double flops_per_slice = 0, flops_block = 0, gemm_flops_block = 0, flops_call = 0;
   int n_gemm_block = 0;
+  int n_scale_slots = 0;
 };
 
 // Host-only compilation; returns QX_OK or an error with a message.

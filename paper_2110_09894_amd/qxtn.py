@@ -31,7 +31,7 @@ PRECISIONS = {"c64": QX_C64, "split_bf16": QX_SPLIT_BF16, "split_fp16": QX_SPLIT
 EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_contract", "qx_plan_destroy", "qx_last_error",
             "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm"]
 
-OPCLASSES = ["gemm", "simt", "dot", "permute", "slice_sum", "gather"]
+OPCLASSES = ["gemm", "simt", "dot", "permute", "slice_sum", "gather", "scale"]
 
 
 class QxError(RuntimeError):

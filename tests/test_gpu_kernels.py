@@ -77,3 +77,19 @@ def test_cgemm_c64(M, N, K, akc, bkc):
     assert np.all(np.abs(got - want) <= 2 * K * 2.0 ** -23 * bound + 1e-30)
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert rel < 2e-6
+
+
+# Split precision: A ~ Ah + Al with 8 (BF16) or 11 (FP16) significant bits per part; the product drops
+# Al Bl, so the normwise error is a few units of 2^-16 (BF16) or 2^-22 (FP16), plus FP32 accumulation.
+SPLIT_REL = {"split_bf16": 6e-5, "split_fp16": 4e-6}
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("M,N,K", [(128, 128, 128), (256, 512, 64), (64, 64, 16), (37, 53, 19), (300, 129, 257),
+                                   (512, 512, 512)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (True, False)])
+def test_cgemm_split(precision, M, N, K, akc, bkc):
+    got, want, bound = _gemm_case(M, N, K, akc, bkc, 2, M * 5 + N * 11 + K, precision)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < SPLIT_REL[precision], rel
+    assert np.all(np.abs(got - want) <= 64 * SPLIT_REL[precision] * bound + 1e-30)

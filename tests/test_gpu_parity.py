@@ -154,3 +154,49 @@ def test_errors_leave_plan_usable():
     got = gpu_amplitudes(plan, xs)
     want = oracle.amplitudes_statevector(w.circuit(), xs)
     assert rms_err(got, want) < TOL_C64
+
+
+TOL_SPLIT = 1e-4
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
+def test_split_precision_c1_and_sliced(precision):
+    w = configs.get("c1")
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs), precision=precision)
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_statevector(w.circuit(), xs)
+    assert rms_err(got, want) < TOL_SPLIT
+    circ = random_grid_circuit(3, 3, 6, 21)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=2)
+    sl = tree_trimming(net, tree, 4, seed=2)
+    xs = random_bitstrings(9, 16, 5)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=16, precision=precision, slice_batch_log2=2)
+    assert rms_err(gpu_amplitudes(plan, xs), oracle.amplitudes_statevector(circ, xs)) < TOL_SPLIT
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
+def test_split_precision_c2_slice(precision):
+    w = configs.get("c2")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), precision=precision)
+    got = gpu_amplitudes(plan, xs, (5, 6))
+    pick = np.arange(3, len(xs), 32)
+    want = np.array([oracle.contract_slice(net, tree, xs[i], sl, 5) for i in pick])
+    assert rms_err(got[pick], want) < TOL_SPLIT
+
+
+def test_mirror_circuit_split_bf16():
+    circ = mirror_circuit(5, 6, 6, 23)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=3)
+    sl = tree_trimming(net, tree, 6, seed=3)
+    xs = np.concatenate([[0], random_bitstrings(30, 7, 7)]).astype(np.uint64)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=8, precision="split_bf16")
+    got = gpu_amplitudes(plan, xs)
+    assert abs(got[0] - 1) < 1e-4
+    assert np.max(np.abs(got[1:])) < 1e-4

@@ -235,7 +235,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
   if (opt.slice_batch_log2 >= 0) {
     st = compile_plan(net, tree, sliced, n_sliced, opt, opt.slice_batch_log2, p->pc, err);
   } else {
-    const int64_t limit = opt.hbm_budget_bytes > 0 ? opt.hbm_budget_bytes : (int64_t)96 << 30;
+    const int64_t limit = opt.hbm_budget_bytes > 0 ? opt.hbm_budget_bytes : (int64_t)24 << 30;
     double best = 1e300;
     int best_js = -1;
     st = QX_OK;
@@ -491,6 +491,7 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   // 16-byte vector loads along k need even strides and an aligned base
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
+  gemm_epilogue_setup(g);
   const int tile = (M >= 128 && N >= 128) ? GEMM_TILE_128x128 : GEMM_TILE_64x64;
   HIP_TRY(launch_gemm(g, precision, tile, (hipStream_t)stream));
   return QX_OK;

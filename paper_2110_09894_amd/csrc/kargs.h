@@ -34,17 +34,34 @@ struct SimtArgs {
 
 // Batched complex matrix product on the matrix cores:
 //   C[z][m][n] = sum_k A[z][m][k] B[z][k][n],  z = item * 2^nh + h
+// Element addressing has two modes.  Linear: A(m, k) at m*a_ms + k*a_ks, B(k, n)
+// at k*b_ks + n*b_ns, C(m, n) at m*c_ms + n.  Bit-scattered (bits != 0, M, N, K
+// powers of two): every bit of m, n, k has its own stride in each operand, so
+// any index order of a dim-2 tensor can be read or written in place:
+//   A(m, k) at sum_i bit_i(m) a_rs[i] + sum_j bit_j(k) a_kst[j], etc.
+// a_kc / b_kc: k bits 0..2 are unit-stride-contiguous (8 consecutive k values
+// are 8 consecutive elements), which enables 16-byte loads along k.
+#define QX_GEMM_BITS 32
 struct GemmArgs {
   const QxCplx *a, *b;
   QxCplx *c;
   int64_t M, N, K;
-  int64_t a_ms, a_ks, b_ks, b_ns, c_ms;  // c_ns == 1; one of (a_ms, a_ks) and of (b_ks, b_ns) is 1
+  int64_t a_ms, a_ks, b_ks, b_ns, c_ms;  // linear mode
   int64_t a_item, b_item, c_item;
   const int64_t *a_gather, *b_gather;
   int32_t n_items, nh;                   // nh = number of shared-slice bits
   int32_t vec_a, vec_b;                  // 16-byte vector loads allowed along k (alignment)
   const float *a_scale, *b_scale;        // split FP16: power-of-two operand scales (null = 1)
+  int32_t bits, nm, nn, nk;              // bit-scattered mode and log2 of M, N, K
+  int32_t a_kc, b_kc;
+  // epilogue: the ten bits of a 32x32 block in ascending order of output stride,
+  // each with its output stride and its contribution to the block-local m / n
+  int64_t ep_st[10];
+  int32_t ep_lm[10], ep_ln[10];
   int64_t a_hs[QX_MAX_HBITS], b_hs[QX_MAX_HBITS], c_hs[QX_MAX_HBITS];
+  int64_t a_rs[QX_GEMM_BITS], a_kst[QX_GEMM_BITS];
+  int64_t b_rs[QX_GEMM_BITS], b_kst[QX_GEMM_BITS];
+  int64_t c_mst[QX_GEMM_BITS], c_nst[QX_GEMM_BITS];
 };
 
 // Long inner products (root of a slice's tree): one work-group per output element.

@@ -9,6 +9,8 @@
 //   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)
 #include <hip/hip_runtime.h>
+
+#include <utility>
 #include "kargs.h"
 #include "kernels.h"
 #include "qxtn.h"
@@ -66,50 +68,116 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
 // ---------------------------------------------------------------------------
 // Operand tile loader shared by the matrix-product kernels.  A tile is ROWS
 // rows x 16 k of complex64; every chunk is 8 consecutive k of one row.  For a
-// k-contiguous operand a thread reads its chunk with 16-byte loads; for a
-// row-contiguous operand consecutive lanes take consecutive rows, so every
-// 8-byte load instruction is coalesced across the wave.
+// k-contiguous operand a thread reads its chunk with 16-byte loads; otherwise
+// consecutive lanes take consecutive rows, so a row-contiguous operand is read
+// with coalesced 8-byte loads.  Row offsets are fixed per thread for the whole
+// kernel; the k offset of the tile origin is recomputed per k tile.
 // ---------------------------------------------------------------------------
+__device__ inline int64_t scatter_bits(int64_t v, const int64_t* st, int n) {
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i)
+    if ((v >> i) & 1) off += st[i];
+  return off;
+}
+
+struct OperandView {
+  const QxCplx* X;
+  int64_t rows, K;
+  int64_t ld_r, ld_k;        // linear mode
+  const int64_t *rs, *ks;    // bit mode
+  int nr, nk;
+  bool bits, kc, vec;
+};
+
 template <int ROWS, bool KC>
 struct TileLoader {
   static constexpr int BK = 16;
   static constexpr int CH = ROWS * (BK / 8);
   static constexpr int P = (CH + 255) / 256;
+  int64_t roff[P];           // offset of the chunk's row
+  int64_t kgoff[P];          // offset of the chunk's first k within the tile
+  int rloc[P], kgl[P];
+  bool rok[P];
   __device__ static inline void row_kg(int c, int& r, int& kg) {
     r = KC ? c / (BK / 8) : c % ROWS;
     kg = KC ? c % (BK / 8) : c / ROWS;
   }
-  __device__ static inline void load(const QxCplx* __restrict__ X, int64_t rows, int64_t K, int64_t ld_r,
-                                     int64_t ld_k, int64_t r0, int64_t k0, bool vec, int tid,
-                                     QxCplx (&reg)[P][8]) {
+  __device__ inline int64_t koff(const OperandView& v, int64_t k) const {
+    return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
+  }
+  __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
+    const int64_t rbase = v.bits ? scatter_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
 #pragma unroll
     for (int ps = 0; ps < P; ++ps) {
       const int c = tid + ps * 256;
-      if (c >= CH) continue;
-      int r, kg;
-      row_kg(c, r, kg);
-      const int64_t row = r0 + r, kb = k0 + kg * 8;
-      if (KC) {
-        const QxCplx* src = X + row * ld_r + kb;
-        if (vec && row < rows && kb + 8 <= K) {
+      int r = 0, kg = 0;
+      if (c < CH) row_kg(c, r, kg);
+      rloc[ps] = r;
+      kgl[ps] = kg;
+      rok[ps] = c < CH && r0 + r < v.rows;
+      roff[ps] = rbase + (v.bits ? scatter_bits(r, v.rs, v.nr) : (int64_t)r * v.ld_r);
+      kgoff[ps] = koff(v, kg * 8);
+    }
+  }
+  // offset of k0 (a multiple of 16): bits 4 and up
+  __device__ inline int64_t kbase(const OperandView& v, int64_t k0) const { return koff(v, k0); }
+  __device__ inline void load(const OperandView& v, int64_t k0, QxCplx (&reg)[P][8]) const {
+    const int64_t kb0 = kbase(v, k0);
 #pragma unroll
-          for (int j = 0; j < 8; j += 2) {
-            v4f v = *(const v4f*)(src + j);
-            reg[ps][j] = {v[0], v[1]};
-            reg[ps][j + 1] = {v[2], v[3]};
-          }
-        } else {
+    for (int ps = 0; ps < P; ++ps) {
+      const int64_t kb = k0 + kgl[ps] * 8;
+      const QxCplx* src = v.X + roff[ps] + kb0 + kgoff[ps];
+      if (KC && v.vec && rok[ps] && kb + 8 <= v.K) {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) reg[ps][j] = (row < rows && kb + j < K) ? src[j] : QxCplx{0.f, 0.f};
+        for (int j = 0; j < 8; j += 2) {
+          v4f x = *(const v4f*)(src + j);
+          reg[ps][j] = {x[0], x[1]};
+          reg[ps][j + 1] = {x[2], x[3]};
         }
+      } else if (KC) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[j] : QxCplx{0.f, 0.f};
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          reg[ps][j] = (row < rows && kb + j < K) ? X[(kb + j) * ld_k + row] : QxCplx{0.f, 0.f};
+        for (int j = 0; j < 8; ++j) {
+          const int64_t jo = v.bits ? ((j & 1) ? v.ks[0] : 0) + ((j & 2) ? v.ks[1] : 0) + ((j & 4) ? v.ks[2] : 0)
+                                    : (int64_t)j * v.ld_k;
+          reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[jo] : QxCplx{0.f, 0.f};
+        }
       }
     }
   }
 };
+
+__device__ inline OperandView view_a(const GemmArgs& p, const QxCplx* X) {
+  OperandView v;
+  v.X = X; v.rows = p.M; v.K = p.K; v.ld_r = p.a_ms; v.ld_k = p.a_ks; v.rs = p.a_rs; v.ks = p.a_kst;
+  v.nr = p.nm; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.a_kc != 0 : p.a_ks == 1; v.vec = p.vec_a != 0;
+  return v;
+}
+__device__ inline OperandView view_b(const GemmArgs& p, const QxCplx* X) {
+  OperandView v;
+  v.X = X; v.rows = p.N; v.K = p.K; v.ld_r = p.b_ns; v.ld_k = p.b_ks; v.rs = p.b_rs; v.ks = p.b_kst;
+  v.nr = p.nn; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.b_kc != 0 : p.b_ks == 1; v.vec = p.vec_b != 0;
+  return v;
+}
+
+// Output offset of (m, n): m0 / n0 are tile origins, lm / ln offsets inside the tile.
+struct OutMap {
+  int64_t mbase, nbase;
+  __device__ inline int64_t m(const GemmArgs& p, int64_t lm) const {
+    return p.bits ? mbase + scatter_bits(lm, p.c_mst, p.nm) : mbase + lm * p.c_ms;
+  }
+  __device__ inline int64_t n(const GemmArgs& p, int64_t ln) const {
+    return p.bits ? nbase + scatter_bits(ln, p.c_nst, p.nn) : nbase + ln;
+  }
+};
+__device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
+  OutMap o;
+  o.mbase = p.bits ? scatter_bits(m0, p.c_mst, p.nm) : m0 * p.c_ms;
+  o.nbase = p.bits ? scatter_bits(n0, p.c_nst, p.nn) : n0;
+  return o;
+}
 
 // Work-group -> (batch item, hyper index, tile) with an XCD-aware order:
 // hardware deals work-groups round-robin over the 8 XCDs, so each XCD gets a
@@ -140,6 +208,60 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
   return tc;
 }
 
+// Epilogue: each 32x32 accumulator block goes through LDS and is stored in the
+// order of ascending output address, so the stores form contiguous runs for
+// any output index order.  Element e of a block (10 bits, ordered by output
+// stride) is split into a lane part (bits 0..5) and a store-step part (bits
+// 6..9); both offsets are sums of precomputed per-bit strides.
+// stage: per-wave LDS area of 32 x 33 complex.
+template <int FM, int FN, int WM, int WN, bool UNROLL>
+__device__ inline void store_blocks(const GemmArgs& p, QxCplx* __restrict__ C, const OutMap& om, int64_t m0,
+                                    int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
+                                    const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
+  const int lrow = lane & 31, g = lane >> 5;
+  int lm_lane = 0, ln_lane = 0;
+  int64_t off_lane = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if ((lane >> b) & 1) {
+      lm_lane += p.ep_lm[b];
+      ln_lane += p.ep_ln[b];
+      off_lane += p.ep_st[b];
+    }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        stage[(8 * (i / 4) + 4 * g + (i % 4)) * 33 + lrow] = QxCplx{cr[a][b][i] * scale, ci[a][b][i] * scale};
+      __syncthreads();
+      const int64_t lm0 = wm * WM + a * 32, ln0 = wn * WN + b * 32;
+      QxCplx* __restrict__ Cb = C + om.m(p, lm0) + om.n(p, ln0) + off_lane;
+      auto put = [&](int j) {
+        int lm = lm_lane, ln = ln_lane;
+        int64_t off = 0;
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2)
+          if ((j >> b2) & 1) {
+            lm += p.ep_lm[6 + b2];
+            ln += p.ep_ln[6 + b2];
+            off += p.ep_st[6 + b2];
+          }
+        if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) Cb[off] = stage[lm * 33 + ln];
+      };
+      // a rolled loop keeps the FP32 kernel's registers low enough for two waves per SIMD
+      if (UNROLL) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) put(j);
+      } else {
+#pragma unroll 1
+        for (int j = 0; j < 16; ++j) put(j);
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Complex GEMM on FP32 matrix cores (v_mfma_f32_32x32x2_f32).
 // Work-group tile BM x BN, 4 waves in a 2x2 grid, K tile of 16 complex values.
@@ -157,8 +279,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   constexpr int FM = WM / 32, FN = WN / 32;
   using LA = TileLoader<BM, A_KC>;
   using LB = TileLoader<BN, B_KC>;
-  __shared__ __attribute__((aligned(16))) QxCplx As[2][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) QxCplx Bs[2][BN * PITCH];
+  // one LDS area: double-buffered operand tiles, reused by the epilogue's
+  // per-wave 32 x 33 staging blocks
+  constexpr int SA = 2 * BM * PITCH, SB = 2 * BN * PITCH, SE = 4 * 32 * 33;
+  __shared__ __attribute__((aligned(16))) QxCplx smem[(SA + SB) > SE ? (SA + SB) : SE];
+  QxCplx (*As)[BM * PITCH] = reinterpret_cast<QxCplx (*)[BM * PITCH]>(smem);
+  QxCplx (*Bs)[BN * PITCH] = reinterpret_cast<QxCplx (*)[BN * PITCH]>(smem + SA);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -167,10 +293,15 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   const QxCplx* __restrict__ B = p.b + tc.boff;
   const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
 
+  const OperandView va = view_a(p, A), vb = view_b(p, B);
+  LA la;
+  LB lb;
+  la.init(va, m0, tid);
+  lb.init(vb, n0, tid);
   QxCplx ra[LA::P][8], rb[LB::P][8];
   auto load_tiles = [&](int64_t k0) {
-    LA::load(A, p.M, p.K, p.a_ms, p.a_ks, m0, k0, p.vec_a, tid, ra);
-    LB::load(B, p.N, p.K, p.b_ns, p.b_ks, n0, k0, p.vec_b, tid, rb);
+    la.load(va, k0, ra);
+    lb.load(vb, k0, rb);
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
@@ -265,16 +396,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   }
 
   QxCplx* __restrict__ C = p.c + tc.coff;
-#pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t m = m0 + wm * WM + a * 32 + 8 * (i / 4) + 4 * g + (i % 4);
-        const int64_t n = n0 + wn * WN + b * 32 + lrow;
-        if (m < p.M && n < p.N) C[m * p.c_ms + n] = QxCplx{cr[a][b][i], ci[a][b][i]};
-      }
+  const OutMap om = out_map(p, m0, n0);
+  store_blocks<FM, FN, WM, WN, false>(p, C, om, m0, n0, wm, wn, lane, cr, ci, 1.f, smem + wave * (32 * 33));
 }
 
 // ---------------------------------------------------------------------------
@@ -317,8 +440,13 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
   constexpr int FM = WM / 32, FN = WN / 32;
   using LA = TileLoader<BM, A_KC>;
   using LB = TileLoader<BN, B_KC>;
-  __shared__ __attribute__((aligned(16))) T As[2][4][BM * P16];
-  __shared__ __attribute__((aligned(16))) T Bs[2][4][BN * P16];
+  // one LDS area: double-buffered hi/lo operand planes, reused by the
+  // epilogue's per-wave 32 x 33 complex staging blocks
+  constexpr int SA = 2 * 4 * BM * P16, SB = 2 * 4 * BN * P16;     // 16-bit elements
+  constexpr int SE = 4 * 32 * 33 * 4;                               // complex64 as 16-bit units
+  __shared__ __attribute__((aligned(16))) T smem[(SA + SB) > SE ? (SA + SB) : SE];
+  T (*As)[4][BM * P16] = reinterpret_cast<T (*)[4][BM * P16]>(smem);
+  T (*Bs)[4][BN * P16] = reinterpret_cast<T (*)[4][BN * P16]>(smem + SA);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -329,10 +457,15 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
   const float sa = p.a_scale ? p.a_scale[0] : 1.f;
   const float sb = p.b_scale ? p.b_scale[0] : 1.f;
 
+  const OperandView va = view_a(p, A), vb = view_b(p, B);
+  LA la;
+  LB lb;
+  la.init(va, m0, tid);
+  lb.init(vb, n0, tid);
   QxCplx ra[LA::P][8], rb[LB::P][8];
   auto load_tiles = [&](int64_t k0) {
-    LA::load(A, p.M, p.K, p.a_ms, p.a_ks, m0, k0, p.vec_a, tid, ra);
-    LB::load(B, p.N, p.K, p.b_ns, p.b_ks, n0, k0, p.vec_b, tid, rb);
+    la.load(va, k0, ra);
+    lb.load(vb, k0, rb);
   };
   // split 8 complex values into the four planes and store 16 bytes per plane
   auto split_store = [&](T* p0, T* p1, T* p2, T* p3, const QxCplx (&v)[8], float sc) {
@@ -463,16 +596,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
 
   const float unscale = 1.f / (sa * sb);
   QxCplx* __restrict__ C = p.c + tc.coff;
-#pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t m = m0 + wm * WM + a * 32 + 8 * (i / 4) + 4 * g + (i % 4);
-        const int64_t n = n0 + wn * WN + b * 32 + lrow;
-        if (m < p.M && n < p.N) C[m * p.c_ms + n] = QxCplx{cr[a][b][i] * unscale, ci[a][b][i] * unscale};
-      }
+  const OutMap om = out_map(p, m0, n0);
+  store_blocks<FM, FN, WM, WN, true>(p, C, om, m0, n0, wm, wn, lane, cr, ci, unscale,
+                               reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
 }
 
 // ---------------------------------------------------------------------------
@@ -491,18 +617,22 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
     if (i < p.n_out && ((o >> i) & 1)) { ao += p.a_os[i]; bo += p.b_os[i]; }
   const QxCplx* __restrict__ A = p.a + ao;
   const QxCplx* __restrict__ B = p.b + bo;
-  QxCplx acc = {0.f, 0.f};
-  const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (p.K & 1) == 0;
+  // four independent partial sums per lane keep the sequential chains short
+  QxCplx acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f}, acc2 = {0.f, 0.f}, acc3 = {0.f, 0.f};
+  const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (p.K & 3) == 0;
   if (vec) {
-    for (int64_t k = 2 * (int64_t)threadIdx.x; k < p.K; k += 2 * blockDim.x) {
-      v4f va = *(const v4f*)(A + k);
-      v4f vb = *(const v4f*)(B + k);
-      acc = cmul_acc(acc, QxCplx{va[0], va[1]}, QxCplx{vb[0], vb[1]});
-      acc = cmul_acc(acc, QxCplx{va[2], va[3]}, QxCplx{vb[2], vb[3]});
+    for (int64_t k = 4 * (int64_t)threadIdx.x; k < p.K; k += 4 * blockDim.x) {
+      const v4f a0 = *(const v4f*)(A + k), a1 = *(const v4f*)(A + k + 2);
+      const v4f b0 = *(const v4f*)(B + k), b1 = *(const v4f*)(B + k + 2);
+      acc0 = cmul_acc(acc0, QxCplx{a0[0], a0[1]}, QxCplx{b0[0], b0[1]});
+      acc1 = cmul_acc(acc1, QxCplx{a0[2], a0[3]}, QxCplx{b0[2], b0[3]});
+      acc2 = cmul_acc(acc2, QxCplx{a1[0], a1[1]}, QxCplx{b1[0], b1[1]});
+      acc3 = cmul_acc(acc3, QxCplx{a1[2], a1[3]}, QxCplx{b1[2], b1[3]});
     }
   } else {
-    for (int64_t k = threadIdx.x; k < p.K; k += blockDim.x) acc = cmul_acc(acc, A[k], B[k]);
+    for (int64_t k = threadIdx.x; k < p.K; k += blockDim.x) acc0 = cmul_acc(acc0, A[k], B[k]);
   }
+  QxCplx acc = {(acc0.x + acc1.x) + (acc2.x + acc3.x), (acc0.y + acc1.y) + (acc2.y + acc3.y)};
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     acc.x += __shfl_xor(acc.x, off, 64);
@@ -655,7 +785,8 @@ static hipError_t launch_gemm_tile(const GemmArgs& a, hipStream_t s) {
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
   if (nwg <= 0) return hipSuccess;
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool akc = a.a_ks == 1, bkc = a.b_ks == 1;
+  const bool akc = a.bits ? a.a_kc != 0 : a.a_ks == 1;
+  const bool bkc = a.bits ? a.b_kc != 0 : a.b_ks == 1;
   dim3 grid((unsigned)nwg), block(256);
   if (PREC == QX_C64) {
     if (akc && bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, true>), grid, block, 0, s, a);
@@ -723,6 +854,35 @@ hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n_items + 255) / 256));
   hipLaunchKernelGGL(k_slice_sum, grid, dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+void gemm_epilogue_setup(GemmArgs& g) {
+  // the ten bits of a 32x32 block (m 0..4, n 0..4) in ascending order of output stride
+  int64_t st[10];
+  int id[10];
+  for (int i = 0; i < 5; ++i) {
+    id[i] = i;
+    id[5 + i] = 8 + i;
+    if (g.bits) {
+      st[i] = i < g.nm ? g.c_mst[i] : ((int64_t)1 << 62) + i;
+      st[5 + i] = i < g.nn ? g.c_nst[i] : ((int64_t)1 << 62) + 5 + i;
+    } else {
+      st[i] = g.c_ms << i;
+      st[5 + i] = (int64_t)1 << i;
+    }
+  }
+  for (int i = 1; i < 10; ++i)
+    for (int j = i; j > 0 && st[j] < st[j - 1]; --j) {
+      std::swap(st[j], st[j - 1]);
+      std::swap(id[j], id[j - 1]);
+    }
+  for (int i = 0; i < 10; ++i) {
+    const bool isn = id[i] >= 8;
+    const int bit = isn ? id[i] - 8 : id[i];
+    g.ep_lm[i] = isn ? 0 : 1 << bit;
+    g.ep_ln[i] = isn ? 1 << bit : 0;
+    g.ep_st[i] = st[i] >= ((int64_t)1 << 62) ? 0 : st[i];
+  }
 }
 
 hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s) {

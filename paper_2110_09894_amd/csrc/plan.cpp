@@ -24,7 +24,8 @@
 //         its operands must hold the free and contracted indices as two
 //         contiguous groups at the fast end, else an LDS-tiled permute copies
 //         them into that layout;
-//   DOT   a long inner product when M*N <= 4 and K >= 256;
+//   DOT   long inner products (K >= 256, not a matrix-core product): one
+//         work-group reduces each output, never one thread;
 //   SIMT  otherwise (any layout, one thread per output element).
 #include "plan.h"
 #include "kernels.h"
@@ -250,7 +251,7 @@ struct Compiler {
       const int m = (int)nd.Fa.size(), nb = (int)nd.Fb.size(), k = (int)nd.K.size();
       const bool leaf_fixed = A.has_fixed || B.has_fixed;
       if (!leaf_fixed && m >= 4 && nb >= 4 && k >= 4 && m + nb + k >= 15) nd.cls = CLS_GEMM;
-      else if (!leaf_fixed && k >= 8 && m + nb <= 2) nd.cls = CLS_DOT;
+      else if (!leaf_fixed && k >= 8) nd.cls = CLS_DOT;  // long sums: parallel reduction, never one thread
       else nd.cls = CLS_SIMT;
       if ((int)nd.bits.size() > QX_MAX_BITS) {
         err = "an intermediate has more than 48 indices (including open output and slice indices)";
@@ -280,16 +281,169 @@ struct Compiler {
     return true;
   }
 
-  // K order the sibling already fixes for the parent, if the sibling exists.
-  std::vector<int> sibling_korder(int p, const std::vector<int>& Kq) {
-    const Node& q = nodes[nodes[p].parent];
-    const int sib = q.a == p ? q.b : q.a;
-    std::vector<int> ko = Kq;
-    if (nodes[sib].tensor >= 0) {
-      const Tensor& st = pc.tensors[nodes[sib].tensor];
-      std::sort(ko.begin(), ko.end(), [&](int x, int y) { return pos_in(st, x) < pos_in(st, y); });
+  // Preferred storage order (fastest first) of node p's result for its consumer.
+  // For a matrix-product parent: the contracted indices lowest -- the sibling's
+  // three lowest if they are contracted there, so both operands can be read
+  // k-contiguously -- then the parent's free indices, then the rest.  For a
+  // dot parent the sibling's contracted order must be matched exactly.
+  // Otherwise: the free indices of the larger child first (coalesced writes).
+  std::vector<int> preferred_layout(int p, int ta, int tb) {
+    const Node& nd = nodes[p];
+    const int q = nd.parent;
+    const Tensor& TA = pc.tensors[ta];
+    const Tensor& TB = pc.tensors[tb];
+    const Tensor& big = TA.elems() >= TB.elems() ? TA : TB;
+    const Tensor& small = TA.elems() >= TB.elems() ? TB : TA;
+    std::vector<int> ff;
+    auto push = [&](int lab) {
+      if (contains(nd.bits, lab) && std::find(ff.begin(), ff.end(), lab) == ff.end()) ff.push_back(lab);
+    };
+    if (q >= 0 && (nodes[q].cls == CLS_GEMM || nodes[q].cls == CLS_DOT)) {
+      const Node& Q = nodes[q];
+      const std::vector<int> vis = visible(nd, Q.batched);
+      const std::vector<int> kq = set_and(vis, Q.K);
+      const std::vector<int> fq = set_minus(set_minus(vis, Q.K), Q.H);
+      const int sib = Q.a == p ? Q.b : Q.a;
+      bool matched = false;
+      if (nodes[sib].tensor >= 0) {
+        const Tensor& st = pc.tensors[nodes[sib].tensor];
+        if (Q.cls == CLS_DOT) {
+          std::vector<int> ko = kq;
+          std::sort(ko.begin(), ko.end(), [&](int x, int y) { return pos_in(st, x) < pos_in(st, y); });
+          for (int lab : ko) push(lab);
+          matched = true;
+        } else if (st.lay.size() >= 3 && contains(kq, st.lay[0]) && contains(kq, st.lay[1]) &&
+                   contains(kq, st.lay[2])) {
+          for (int i = 0; i < 3; ++i) push(st.lay[i]);
+          matched = true;
+        }
+      }
+      if (!matched || Q.cls == CLS_GEMM) {
+        for (int lab : big.lay)
+          if (contains(kq, lab)) push(lab);
+        for (int lab : small.lay)
+          if (contains(kq, lab)) push(lab);
+      }
+      for (int lab : big.lay)
+        if (contains(fq, lab)) push(lab);
+      for (int lab : small.lay)
+        if (contains(fq, lab)) push(lab);
     }
-    return ko;
+    for (int lab : big.lay) push(lab);
+    for (int lab : small.lay) push(lab);
+    return ff;
+  }
+
+  // Matrix product in bit-scattered mode: operands are read in their stored
+  // layouts and the result is written in the layout its consumer prefers.
+  void emit_gemm(Node& nd, int ta, int tb, Tensor& out, Op& op, double items) {
+    const int p = (int)(&nd - nodes.data());
+    out.lay = preferred_layout(p, ta, tb);
+    // the N side (whose rows vary across lanes in the epilogue) owns the lowest output index
+    bool a_is_n = nd.Fa.size() > nd.Fb.size();
+    for (int lab : out.lay) {
+      if (contains(nd.Fa, lab)) { a_is_n = true; break; }
+      if (contains(nd.Fb, lab)) { a_is_n = false; break; }
+    }
+    const int tA = a_is_n ? tb : ta, tB = a_is_n ? ta : tb;
+    const std::vector<int>& FA = a_is_n ? nd.Fb : nd.Fa;
+    const std::vector<int>& FB = a_is_n ? nd.Fa : nd.Fb;
+    const Tensor& XA = pc.tensors[tA];
+    const Tensor& XB = pc.tensors[tB];
+    const View va = view(XA, nd.batched), vb = view(XB, nd.batched);
+    op.in_a = tA;
+    op.in_b = tB;
+    op.gather_a = add_gather(tA, va);
+    op.gather_b = add_gather(tB, vb);
+    auto by_out = [&](std::vector<int> v) {
+      std::sort(v.begin(), v.end(), [&](int x, int y) { return pos_in(out, x) < pos_in(out, y); });
+      return v;
+    };
+    const std::vector<int> mlab = by_out(FA), nlab = by_out(FB);
+    // k numbering: three unit-stride k bits first when an operand has them lowest
+    auto low3 = [&](const Tensor& t) {
+      return t.lay.size() >= 3 && contains(nd.K, t.lay[0]) && contains(nd.K, t.lay[1]) &&
+             contains(nd.K, t.lay[2]);
+    };
+    const bool a3 = low3(XA), b3 = low3(XB);
+    bool kca = false, kcb = false;
+    std::vector<int> klab;
+    const Tensor* kref = XA.elems() >= XB.elems() ? &XA : &XB;
+    if (a3 && b3 && std::equal(XA.lay.begin(), XA.lay.begin() + 3, XB.lay.begin())) {
+      kca = kcb = true;
+      klab.assign(XA.lay.begin(), XA.lay.begin() + 3);
+    } else if (a3 && (!b3 || XA.elems() >= XB.elems())) {
+      kca = true;
+      klab.assign(XA.lay.begin(), XA.lay.begin() + 3);
+      kref = &XA;
+    } else if (b3) {
+      kcb = true;
+      klab.assign(XB.lay.begin(), XB.lay.begin() + 3);
+      kref = &XB;
+    }
+    std::vector<int> krest = nd.K;
+    std::sort(krest.begin(), krest.end(), [&](int x, int y) { return pos_in(*kref, x) < pos_in(*kref, y); });
+    for (int lab : krest)
+      if (std::find(klab.begin(), klab.end(), lab) == klab.end()) klab.push_back(lab);
+    std::vector<int> horder = nd.H;
+    std::sort(horder.begin(), horder.end(), [&](int x, int y) { return pos_in(XA, x) < pos_in(XA, y); });
+
+    GemmArgs& g = op.gemm;
+    std::memset(&g, 0, sizeof(g));
+    g.bits = 1;
+    g.nm = (int)mlab.size();
+    g.nn = (int)nlab.size();
+    g.nk = (int)klab.size();
+    g.M = (int64_t)1 << g.nm;
+    g.N = (int64_t)1 << g.nn;
+    g.K = (int64_t)1 << g.nk;
+    for (int i = 0; i < g.nm; ++i) {
+      g.a_rs[i] = (int64_t)1 << pos_in(XA, mlab[i]);
+      g.c_mst[i] = (int64_t)1 << pos_in(out, mlab[i]);
+    }
+    for (int i = 0; i < g.nn; ++i) {
+      g.b_rs[i] = (int64_t)1 << pos_in(XB, nlab[i]);
+      g.c_nst[i] = (int64_t)1 << pos_in(out, nlab[i]);
+    }
+    for (int j = 0; j < g.nk; ++j) {
+      g.a_kst[j] = (int64_t)1 << pos_in(XA, klab[j]);
+      g.b_kst[j] = (int64_t)1 << pos_in(XB, klab[j]);
+    }
+    g.a_kc = kca;
+    g.b_kc = kcb;
+    // 16-byte loads need 8-element alignment: arena tensors are 256-byte aligned and every
+    // non-k stride of a k-contiguous operand is a multiple of 8
+    g.vec_a = kca && (!XA.is_leaf || XA.leaf_off % 8 == 0);
+    g.vec_b = kcb && (!XB.is_leaf || XB.leaf_off % 8 == 0);
+    g.a_item = XA.batched ? XA.elems() : 0;
+    g.b_item = XB.batched ? XB.elems() : 0;
+    g.n_items = (int)items;
+    g.nh = (int)horder.size();
+    for (size_t i = 0; i < horder.size(); ++i) {
+      g.a_hs[i] = (int64_t)1 << pos_in(XA, horder[i]);
+      g.b_hs[i] = (int64_t)1 << pos_in(XB, horder[i]);
+      g.c_hs[i] = (int64_t)1 << pos_in(out, horder[i]);
+    }
+    gemm_epilogue_setup(g);
+    op.kind = OP_GEMM;
+    if (pc.precision == QX_SPLIT_FP16) {
+      op.scale_slot = pc.n_scale_slots;
+      pc.n_scale_slots += 2;
+      for (int side = 0; side < 2; ++side) {
+        const int ti = side == 0 ? tA : tB;
+        Op am;
+        am.kind = OP_ABSMAX;
+        am.phase = pc.tensors[ti].phase;
+        am.in_a = ti;
+        am.out = -1;
+        am.scale_slot = op.scale_slot + side;
+        std::memset(&am.absmax, 0, sizeof(am.absmax));
+        am.bytes = 8.0 * (double)pc.tensors[ti].elems() * (pc.tensors[ti].batched ? pc.max_b : 1);
+        ops.push_back(am);
+      }
+    }
+    op.flops = 8.0 * (double)g.M * g.N * g.K * std::ldexp(1.0, g.nh) * items;
+    op.tile = (g.M >= 128 && g.N >= 128) ? 0 : 1;
   }
 
   bool emit_node(int p) {
@@ -304,8 +458,10 @@ struct Compiler {
     op.phase = nd.phase;
     const double items = nd.batched ? pc.max_b : 1;
     const int q = nd.parent;
-    if (nd.cls == CLS_GEMM || nd.cls == CLS_DOT) {
-      const bool need_kfirst = nd.cls == CLS_DOT;
+    if (nd.cls == CLS_GEMM) {
+      emit_gemm(nd, ta, tb, out, op, items);
+    } else if (nd.cls == CLS_DOT) {
+      const bool need_kfirst = true;
       bool ka = false, kb = false;
       std::vector<int> koa, kob, foa, fob;
       bool ra = ready(pc.tensors[ta], nd.Fa, nd.K, ka, koa, foa) && (!need_kfirst || ka);
@@ -323,88 +479,17 @@ struct Compiler {
       } else if (!rb) {
         tb = emit_permute(tb, koa, nd.Fb);
       }
-      ready(pc.tensors[ta], nd.Fa, nd.K, ka, koa, foa);
-      ready(pc.tensors[tb], nd.Fb, nd.K, kb, kob, fob);
       const View va = view(pc.tensors[ta], nd.batched), vb = view(pc.tensors[tb], nd.batched);
       op.in_a = ta;
       op.in_b = tb;
       op.gather_a = add_gather(ta, va);
       op.gather_b = add_gather(tb, vb);
-      // H order: by position in operand a
       std::vector<int> horder = nd.H;
       std::sort(horder.begin(), horder.end(),
                 [&](int x, int y) { return pos_in(pc.tensors[ta], x) < pos_in(pc.tensors[ta], y); });
       const Tensor& TA = pc.tensors[ta];
       const Tensor& TB = pc.tensors[tb];
-      if (nd.cls == CLS_GEMM) {
-        // choose which operand is the fast (N) side of C
-        bool swap = false;
-        if (q >= 0 && (nodes[q].cls == CLS_GEMM || nodes[q].cls == CLS_DOT)) {
-          const std::vector<int>& Kq = nodes[q].K;
-          if (same_set(nd.Fb, Kq)) swap = false;
-          else if (same_set(nd.Fa, Kq)) swap = true;
-          else swap = nd.Fa.size() > nd.Fb.size();
-        } else {
-          swap = nd.Fa.size() > nd.Fb.size();
-        }
-        const int tA = swap ? tb : ta, tB = swap ? ta : tb;
-        const bool kA = swap ? kb : ka, kB = swap ? ka : kb;
-        const std::vector<int>& fA = swap ? fob : foa;
-        const std::vector<int>& fB = swap ? foa : fob;
-        const int gA = swap ? op.gather_b : op.gather_a, gB = swap ? op.gather_a : op.gather_b;
-        op.in_a = tA;
-        op.in_b = tB;
-        op.gather_a = gA;
-        op.gather_b = gB;
-        out.lay = fB;
-        out.lay.insert(out.lay.end(), fA.begin(), fA.end());
-        out.lay.insert(out.lay.end(), horder.begin(), horder.end());
-        GemmArgs& g = op.gemm;
-        std::memset(&g, 0, sizeof(g));
-        const Tensor& XA = pc.tensors[tA];
-        const Tensor& XB = pc.tensors[tB];
-        const int nk = (int)nd.K.size();
-        g.M = (int64_t)1 << fA.size();
-        g.N = (int64_t)1 << fB.size();
-        g.K = (int64_t)1 << nk;
-        if (kA) { g.a_ks = 1; g.a_ms = g.K; } else { g.a_ms = 1; g.a_ks = g.M; }
-        if (kB) { g.b_ks = 1; g.b_ns = g.K; } else { g.b_ns = 1; g.b_ks = g.N; }
-        g.c_ms = g.N;
-        g.vec_a = kA && g.K % 2 == 0;  // arena offsets are 256-byte aligned; all strides are powers of two >= K
-        g.vec_b = kB && g.K % 2 == 0;
-        g.a_item = XA.batched ? XA.elems() : 0;
-        g.b_item = XB.batched ? XB.elems() : 0;
-        g.n_items = (int)items;
-        g.nh = (int)horder.size();
-        for (size_t i = 0; i < horder.size(); ++i) {
-          g.a_hs[i] = (int64_t)1 << pos_in(XA, horder[i]);
-          g.b_hs[i] = (int64_t)1 << pos_in(XB, horder[i]);
-          g.c_hs[i] = (int64_t)1 << (fA.size() + fB.size() + i);
-        }
-        op.kind = OP_GEMM;
-        if (pc.precision == QX_SPLIT_FP16) {
-          // operand scales: max magnitude of each operand's stored tensor
-          op.scale_slot = pc.n_scale_slots;
-          pc.n_scale_slots += 2;
-          for (int side = 0; side < 2; ++side) {
-            const int ti = side == 0 ? tA : tB;
-            Op am;
-            am.kind = OP_ABSMAX;
-            am.phase = pc.tensors[ti].phase;
-            am.in_a = ti;
-            am.out = -1;
-            am.scale_slot = op.scale_slot + side;
-            std::memset(&am.absmax, 0, sizeof(am.absmax));
-            am.bytes = 8.0 * (double)pc.tensors[ti].elems() * (pc.tensors[ti].batched ? pc.max_b : 1);
-            ops.push_back(am);
-          }
-        }
-        const double flops = 8.0 * (double)g.M * g.N * g.K * std::ldexp(1.0, g.nh) * items;
-        op.flops = flops;
-        op.tile = (g.M >= 128 && g.N >= 128) ? 0 : 1;
-        (void)TA;
-        (void)TB;
-      } else {
+      {
         // DOT: output bits fastest-first = Fb, Fa, H
         out.lay = nd.Fb;
         out.lay.insert(out.lay.end(), nd.Fa.begin(), nd.Fa.end());
@@ -425,35 +510,10 @@ struct Compiler {
         op.flops = 8.0 * (double)d.K * std::ldexp(1.0, d.n_out) * items;
       }
     } else {
-      // SIMT: choose the output layout
+      // SIMT: any layout can be written, so write the one the consumer prefers
       const Tensor& TA = pc.tensors[ta];
       const Tensor& TB = pc.tensors[tb];
-      std::vector<int> ff;
-      if (q >= 0 && (nodes[q].cls == CLS_GEMM || nodes[q].cls == CLS_DOT)) {
-        const Node& Q = nodes[q];
-        const std::vector<int> vis = visible(nd, Q.batched);
-        std::vector<int> kq = set_and(vis, Q.K);
-        kq = sibling_korder(p, kq);
-        const std::vector<int> fq = set_minus(set_minus(vis, Q.K), Q.H);
-        ff = kq;
-        const Tensor& big = TA.elems() >= TB.elems() ? TA : TB;
-        const Tensor& small = TA.elems() >= TB.elems() ? TB : TA;
-        for (int lab : big.lay)
-          if (contains(fq, lab)) ff.push_back(lab);
-        for (int lab : small.lay)
-          if (contains(fq, lab) && std::find(ff.begin(), ff.end(), lab) == ff.end()) ff.push_back(lab);
-        for (int lab : big.lay)
-          if (contains(nd.bits, lab) && std::find(ff.begin(), ff.end(), lab) == ff.end()) ff.push_back(lab);
-        for (int lab : small.lay)
-          if (contains(nd.bits, lab) && std::find(ff.begin(), ff.end(), lab) == ff.end()) ff.push_back(lab);
-      } else {
-        const Tensor& big = TA.elems() >= TB.elems() ? TA : TB;
-        const Tensor& small = TA.elems() >= TB.elems() ? TB : TA;
-        for (int lab : big.lay)
-          if (contains(nd.bits, lab)) ff.push_back(lab);
-        for (int lab : small.lay)
-          if (contains(nd.bits, lab) && std::find(ff.begin(), ff.end(), lab) == ff.end()) ff.push_back(lab);
-      }
+      std::vector<int> ff = preferred_layout(p, ta, tb);
       if (ff.size() != nd.bits.size()) {
         err = "internal: output layout incomplete";
         return false;
@@ -684,7 +744,15 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
               o.out, pc.tensors[o.out].lay.size(), (int)pc.tensors[o.out].batched, o.flops, o.bytes);
       if (o.kind == OP_GEMM)
         fprintf(stderr, " M %lld N %lld K %lld nh %d akc %d bkc %d", (long long)o.gemm.M, (long long)o.gemm.N,
-                (long long)o.gemm.K, o.gemm.nh, (int)(o.gemm.a_ks == 1), (int)(o.gemm.b_ks == 1));
+                (long long)o.gemm.K, o.gemm.nh, o.gemm.a_kc, o.gemm.b_kc);
+      if (o.kind == OP_GEMM) {
+        fprintf(stderr, " ep");
+        for (int j = 0; j < 10; ++j) fprintf(stderr, " %s%d:%lld", o.gemm.ep_lm[j] ? "m" : "n",
+                                             o.gemm.ep_lm[j] ? o.gemm.ep_lm[j] : o.gemm.ep_ln[j],
+                                             (long long)o.gemm.ep_st[j]);
+        fprintf(stderr, " hs");
+        for (int j = 0; j < o.gemm.nh; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_hs[j]);
+      }
       if (o.kind == OP_PERM) {
         fprintf(stderr, " in_pos");
         for (int j = 0; j < o.perm.rank; ++j) fprintf(stderr, " %d", o.perm.in_pos[j]);

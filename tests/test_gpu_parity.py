@@ -134,10 +134,21 @@ def test_c2_one_slice_against_oracle(slice_id):
     xs = w.bitstrings()
     plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs))
     got = gpu_amplitudes(plan, xs, (slice_id, slice_id + 1))
-    pick = np.arange(0, len(xs), 16)
-    want = oracle.slice_values(net, tree, xs[pick[0]], sl, [slice_id])
-    want = np.array([oracle.contract_slice(net, tree, xs[i], sl, slice_id) for i in pick])
-    assert rms_err(got[pick], want) < TOL_C64
+    # one slice, all 256 bitstrings of the workload
+    want = np.array([oracle.contract_slice(net, tree, x, sl, slice_id) for x in xs])
+    assert rms_err(got, want) < TOL_C64
+
+
+def test_c2_full_amplitudes_two_bitstrings():
+    """All 1024 slices summed (Eq. 2) for two bitstrings, against the oracle's slice sum."""
+    w = configs.get("c2")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()[:2]
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=256)
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_sliced(net, tree, xs, sl)
+    assert np.max(np.abs(got - want)) / np.sqrt(np.mean(np.abs(want) ** 2)) < TOL_C64
 
 
 def test_errors_leave_plan_usable():
@@ -185,9 +196,8 @@ def test_split_precision_c2_slice(precision):
     xs = w.bitstrings()
     plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), precision=precision)
     got = gpu_amplitudes(plan, xs, (5, 6))
-    pick = np.arange(3, len(xs), 32)
-    want = np.array([oracle.contract_slice(net, tree, xs[i], sl, 5) for i in pick])
-    assert rms_err(got[pick], want) < TOL_SPLIT
+    want = np.array([oracle.contract_slice(net, tree, x, sl, 5) for x in xs])
+    assert rms_err(got, want) < TOL_SPLIT
 
 
 def test_mirror_circuit_split_bf16():

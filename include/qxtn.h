@@ -75,6 +75,12 @@ typedef struct {
   int32_t slice_batch_log2;    /* sliced indices 0..j-1 vary inside one device pass; -1 = auto */
   int32_t dry_run;             /* non-zero: compile on the host only, touch no device */
   int64_t hbm_budget_bytes;    /* 0 = no limit */
+  int32_t autotune;            /* non-zero: time every matrix-core tile shape that fits each
+                                  per-call / per-block product at plan creation and keep the
+                                  fastest (results cached per shape for the process) */
+  int32_t eager;               /* non-zero: launch every op of every slice block individually;
+                                  0: capture one block's ops in a HIP graph per batch size and
+                                  replay it for every block (always eager while timing is on) */
 } qx_plan_options;
 
 typedef struct {
@@ -109,7 +115,7 @@ typedef struct qx_plan qx_plan;
  *                  or earlier steps.  The last step is the root.
  *   sliced         host int64 [n_sliced] labels to slice; none may be an output
  *                  wire; n_sliced <= 40.
- *   opt            host; NULL = defaults (QX_C64, max_bitstrings 1, auto, 0, 0).
+ *   opt            host; NULL = defaults (QX_C64, max_bitstrings 1, auto, 0, 0, 0, 0).
  *   stream         hipStream_t used for uploads and pre-contraction.
  *   out            receives the plan (owned by the caller; free with qx_plan_destroy).
  */

@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,8 +48,14 @@ struct qx_plan {
   char* d_arena = nullptr;
   int64_t* d_gather = nullptr;
   float* d_misc = nullptr;            // FP16 operand scales, absmax partials, absmax ticket
+  int64_t* d_state = nullptr;         // slice-block state (8 int64) then the FP64 accumulator [max_b][2]
   int64_t device_bytes = 0;
+  bool eager = false;
+  hipStream_t cap_stream = nullptr;   // stream used to capture block programs
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // per batch size
 };
+
+static int64_t state_bytes(const PlanCore& pc) { return 64 + (int64_t)pc.max_b * 16; }
 
 static int64_t misc_bytes(const PlanCore& pc) {
   return ((int64_t)pc.n_scale_slots + ABSMAX_PARTIALS + 64) * 4;
@@ -54,7 +63,7 @@ static int64_t misc_bytes(const PlanCore& pc) {
 
 static int64_t plan_device_bytes(const PlanCore& pc) {
   return ((pc.leaf_pool_elems * 8 + 255) / 256) * 256 + pc.arena_bytes +
-         (int64_t)pc.gathers.size() * pc.max_b * 8 + misc_bytes(pc);
+         (int64_t)pc.gathers.size() * pc.max_b * 8 + misc_bytes(pc) + state_bytes(pc);
 }
 
 static QxCplx* tensor_ptr(qx_plan* p, int tid) {
@@ -78,6 +87,17 @@ static void resolve_pointers(qx_plan* p) {
         op.simt.a = a; op.simt.b = b; op.simt.c = c;
         op.simt.a_gather = gather_ptr(p, op.gather_a);
         op.simt.b_gather = gather_ptr(p, op.gather_b);
+        op.simt.block = (op.fix_a.empty() && op.fix_b.empty()) ? nullptr : p->d_state;
+        op.simt.nfix_a = (int)op.fix_a.size();
+        op.simt.nfix_b = (int)op.fix_b.size();
+        for (size_t i = 0; i < op.fix_a.size(); ++i) {
+          op.simt.fix_ja[i] = op.fix_a[i].j;
+          op.simt.fix_sa[i] = op.fix_a[i].stride;
+        }
+        for (size_t i = 0; i < op.fix_b.size(); ++i) {
+          op.simt.fix_jb[i] = op.fix_b[i].j;
+          op.simt.fix_sb[i] = op.fix_b[i].stride;
+        }
         break;
       case OP_GEMM:
         op.gemm.a = a; op.gemm.b = b; op.gemm.c = c;
@@ -138,34 +158,25 @@ static int op_class(int kind) {
   }
 }
 
-static int64_t fix_offset(const std::vector<FixTerm>& fx, int64_t sbase) {
-  int64_t off = 0;
-  for (const FixTerm& f : fx)
-    if ((sbase >> f.j) & 1) off += f.stride;
-  return off;
-}
-
-static qx_status run_op(qx_plan* p, const Op& op, int B, int64_t sbase, hipStream_t s) {
+// Fixed sliced indices only occur on leaf operands of small contractions,
+// whose kernel adds them from the device-side block state.
+static qx_status run_op(qx_plan* p, const Op& op, int B, hipStream_t s) {
   const bool outb = op.out >= 0 ? p->pc.tensors[op.out].batched : false;
-  const int64_t fa = fix_offset(op.fix_a, sbase), fb = fix_offset(op.fix_b, sbase);
   const double scale = outb ? (double)B / p->pc.max_b : 1.0;
   hipError_t e = timed(p, op_class(op.kind), op.flops * scale, op.bytes * scale, s, [&]() -> hipError_t {
   switch (op.kind) {
     case OP_SIMT: {
       SimtArgs a = op.simt;
-      a.a += fa; a.b += fb;
       if (outb) a.n_items = B;
       return launch_simt(a, s);
     }
     case OP_GEMM: {
       GemmArgs g = op.gemm;
-      g.a += fa; g.b += fb;
       if (outb) g.n_items = B;
       return launch_gemm(g, p->pc.precision, op.tile, s);
     }
     case OP_DOT: {
       DotArgs d = op.dot;
-      d.a += fa; d.b += fb;
       if (outb) d.n_items = B;
       return launch_dot(d, s);
     }
@@ -177,7 +188,6 @@ static qx_status run_op(qx_plan* p, const Op& op, int B, int64_t sbase, hipStrea
     }
     case OP_PERM: {
       PermArgs q = op.perm;
-      q.in += fa;
       if (outb) q.n_items = B;
       return launch_permute(q, s);
     }
@@ -193,6 +203,98 @@ static double est_cost(const PlanCore& pc) {
   const double blocks = std::ldexp(1.0, pc.n_sliced - pc.js);
   const double flops = pc.flops_block * blocks + pc.flops_call;
   return flops / 60e12 + blocks * (pc.n_block + 1) * 6e-6 + pc.n_call * 6e-6;
+}
+
+// One slice block: take the next block, run the block ops, add its slices'
+// values into the plan's FP64 accumulator.  Reads the block from device state
+// only, so the same launches can be captured once and replayed per block.
+static qx_status run_block(qx_plan* p, int B, hipStream_t s) {
+  const PlanCore& pc = p->pc;
+  BlockArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.state = p->d_state;
+  ba.acc = reinterpret_cast<double*>(p->d_state + 8);
+  ba.n_items = B;
+  hipError_t e = timed(p, QX_OPCLASS_SLICESUM, 0.0, 0.0, s, [&] { return launch_block_advance(ba, s); });
+  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("block advance launch: ") + hipGetErrorString(e));
+  for (int i = pc.n_const + pc.n_call; i < (int)pc.ops.size(); ++i) {
+    qx_status r = run_op(p, pc.ops[i], B, s);
+    if (r != QX_OK) return r;
+  }
+  const Tensor& rt = pc.tensors[pc.root];
+  SliceSumArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.root = tensor_ptr(p, pc.root);
+  sa.block = p->d_state;
+  sa.root_item = rt.batched ? rt.elems() : 0;
+  sa.root_gather = gather_ptr(p, pc.root_gather);
+  sa.amp = ba.acc;
+  sa.n_items = B;
+  sa.n_sbits = pc.js;
+  for (int j = 0; j < pc.js; ++j) sa.s_stride[j] = pc.root_sstride[j];
+  const double sbytes = 8.0 * std::ldexp(1.0, pc.js) * B + 32.0 * B;
+  e = timed(p, QX_OPCLASS_SLICESUM, 0.0, sbytes, s, [&] { return launch_slice_sum(sa, s); });
+  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("slice-sum launch: ") + hipGetErrorString(e));
+  return QX_OK;
+}
+
+// Tile autotuner: times every tile shape that fits a product and keeps the
+// fastest; results are cached per (precision, shape, batch, operand modes).
+struct TileKey {
+  int prec, nh, items, akc, bkc;
+  int64_t M, N, K;
+  bool operator<(const TileKey& o) const {
+    return std::tie(prec, nh, items, akc, bkc, M, N, K) < std::tie(o.prec, o.nh, o.items, o.akc, o.bkc, o.M, o.N, o.K);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TileKey, int> g_tune_cache;
+
+static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (int i = p->pc.n_const; i < (int)p->pc.ops.size(); ++i) {
+    Op& op = p->pc.ops[i];
+    if (op.kind != OP_GEMM) continue;
+    const GemmArgs& g = op.gemm;
+    const TileKey key{p->pc.precision, g.nh, g.n_items, g.a_kc, g.b_kc, g.M, g.N, g.K};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        op.tile = it->second;
+        continue;
+      }
+    }
+    int best = op.tile;
+    float best_ms = 1e30f;
+    for (int t = 0; t < GEMM_N_TILES; ++t) {
+      int bm, bn;
+      gemm_tile_dims(t, bm, bn);
+      if (bm > std::max<int64_t>(64, g.M) || bn > std::max<int64_t>(64, g.N)) continue;
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(launch_gemm(g, p->pc.precision, t, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) ms_min = std::min(ms_min, ms);
+      }
+      if (ms_min < best_ms) {
+        best_ms = ms_min;
+        best = t;
+      }
+    }
+    op.tile = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return QX_OK;
 }
 
 extern "C" {
@@ -218,7 +320,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     const int64_t r = net->index_ptr[t + 1] - net->index_ptr[t];
     if (r < 0 || r > 40) return fail(QX_ERR_UNSUPPORTED, "tensor rank must be in 0..40");
   }
-  qx_plan_options opt = {QX_C64, 1, -1, 0, 0};
+  qx_plan_options opt = {QX_C64, 1, -1, 0, 0, 0, 0};
   if (opt_in) opt = *opt_in;
   if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
     return fail(QX_ERR_INVALID_ARG, "unknown precision");
@@ -264,6 +366,15 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
                                           std::to_string(opt.hbm_budget_bytes));
   }
   p->dry = opt.dry_run != 0;
+  p->eager = opt.eager != 0;
+  for (const Op& op : p->pc.ops)
+    if (op.kind != OP_SIMT && (!op.fix_a.empty() || !op.fix_b.empty())) {
+      delete p;
+      return fail(QX_ERR_INVALID_TREE, "internal: fixed sliced index on a non-small contraction");
+    } else if (op.fix_a.size() > 4 || op.fix_b.size() > 4) {
+      delete p;
+      return fail(QX_ERR_UNSUPPORTED, "a leaf carries more than 4 sliced indices");
+    }
   if (!p->dry) {
     hipStream_t s = (hipStream_t)stream;
     auto cleanup = [&](qx_status code, const std::string& m) {
@@ -277,6 +388,10 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(leaves): ") + hipGetErrorString(e));
     if ((e = hipMalloc((void**)&p->d_arena, std::max<int64_t>(256, p->pc.arena_bytes))) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(arena): ") + hipGetErrorString(e));
+    if ((e = hipMalloc((void**)&p->d_state, state_bytes(p->pc))) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMalloc(state): ") + hipGetErrorString(e));
+    if ((e = hipMemsetAsync(p->d_state, 0, state_bytes(p->pc), s)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipMemsetAsync(state): ") + hipGetErrorString(e));
     if ((e = hipMalloc((void**)&p->d_misc, misc_bytes(p->pc))) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(misc): ") + hipGetErrorString(e));
     if ((e = hipMemsetAsync(p->d_misc, 0, misc_bytes(p->pc), s)) != hipSuccess)
@@ -292,7 +407,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
       return cleanup(QX_ERR_HIP, std::string("hipMemcpyAsync(leaves): ") + hipGetErrorString(e));
     resolve_pointers(p);
     for (int i = 0; i < p->pc.n_const; ++i) {
-      qx_status r = run_op(p, p->pc.ops[i], 1, 0, s);
+      qx_status r = run_op(p, p->pc.ops[i], 1, s);
       if (r != QX_OK) {
         std::string m = g_err;
         return cleanup(r, m);
@@ -300,6 +415,16 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("plan pre-contraction: ") + hipGetErrorString(e));
+    if (opt.autotune) {
+      // gather offsets of zero keep every timing launch's reads inside its operands
+      if ((e = hipMemsetAsync(p->d_gather, 0, gb, s)) != hipSuccess)
+        return cleanup(QX_ERR_HIP, std::string("hipMemsetAsync(gather): ") + hipGetErrorString(e));
+      qx_status r = autotune_plan(p, s);
+      if (r != QX_OK) {
+        std::string m = g_err;
+        return cleanup(r, m);
+      }
+    }
   }
   *out = p;
   return QX_OK;
@@ -361,33 +486,54 @@ qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64
     if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("gather launch: ") + hipGetErrorString(e));
   }
   for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
-    qx_status r = run_op(p, pc.ops[i], B, 0, s);
+    qx_status r = run_op(p, pc.ops[i], B, s);
     if (r != QX_OK) return r;
   }
-  const int64_t bsz = (int64_t)1 << pc.js;
   const int64_t first = slice_begin >> pc.js, last = (slice_end - 1) >> pc.js;
-  const Tensor& rt = pc.tensors[pc.root];
+  BlockArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.state = p->d_state;
+  ba.acc = reinterpret_cast<double*>(p->d_state + 8);
+  ba.first_block = first;
+  ba.slice_begin = slice_begin;
+  ba.slice_end = slice_end;
+  ba.js = pc.js;
+  ba.n_items = B;
+  HIP_TRY(launch_block_init(ba, s));
+  const bool use_graph = !p->eager && !p->timing && last > first;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    auto it = p->graphs.find(B);
+    if (it == p->graphs.end()) {
+      if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      qx_status r = run_block(p, B, p->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamEndCapture(p->cap_stream, &graph);
+      if (r != QX_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return r;
+      }
+      if (ce != hipSuccess) return fail(QX_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      hipGraphExec_t ge = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(QX_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      }
+      it = p->graphs.emplace(B, std::make_pair(graph, ge)).first;
+    }
+    exec = it->second.second;
+  }
   for (int64_t bb = first; bb <= last; ++bb) {
-    const int64_t base = bb << pc.js;
-    for (int i = pc.n_const + pc.n_call; i < (int)pc.ops.size(); ++i) {
-      qx_status r = run_op(p, pc.ops[i], B, base, s);
+    if (exec) {
+      HIP_TRY(hipGraphLaunch(exec, s));
+    } else {
+      qx_status r = run_block(p, B, s);
       if (r != QX_OK) return r;
     }
-    SliceSumArgs sa;
-    std::memset(&sa, 0, sizeof(sa));
-    sa.root = tensor_ptr(p, pc.root);
-    sa.root_item = rt.batched ? rt.elems() : 0;
-    sa.root_gather = gather_ptr(p, pc.root_gather);
-    sa.amp = d_amplitudes;
-    sa.n_items = B;
-    sa.n_sbits = pc.js;
-    sa.s_lo = (int)(std::max(slice_begin, base) - base);
-    sa.s_hi = (int)(std::min(slice_end, base + bsz) - base);
-    for (int j = 0; j < pc.js; ++j) sa.s_stride[j] = pc.root_sstride[j];
-    const double sbytes = 8.0 * (sa.s_hi - sa.s_lo) * B + 16.0 * 2 * B;
-    hipError_t e = timed(p, QX_OPCLASS_SLICESUM, 0.0, sbytes, s, [&] { return launch_slice_sum(sa, s); });
-    if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("slice-sum launch: ") + hipGetErrorString(e));
   }
+  HIP_TRY(launch_block_finish(ba, d_amplitudes, s));
   return QX_OK;
 }
 
@@ -436,6 +582,12 @@ void qx_plan_destroy(qx_plan* p) {
     if (p->d_arena) hipFree(p->d_arena);
     if (p->d_gather) hipFree(p->d_gather);
     if (p->d_misc) hipFree(p->d_misc);
+    if (p->d_state) hipFree(p->d_state);
+    for (auto& kv : p->graphs) {
+      hipGraphExecDestroy(kv.second.second);
+      hipGraphDestroy(kv.second.first);
+    }
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     hipSetDevice(cur);
   }
   delete p;
@@ -492,7 +644,7 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
   gemm_epilogue_setup(g);
-  const int tile = (M >= 128 && N >= 128) ? GEMM_TILE_128x128 : GEMM_TILE_64x64;
+  const int tile = gemm_default_tile(M, N);
   HIP_TRY(launch_gemm(g, precision, tile, (hipStream_t)stream));
   return QX_OK;
 }

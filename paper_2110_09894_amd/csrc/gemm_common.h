@@ -1,0 +1,220 @@
+// Device code shared by the matrix-core GEMM kernels (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kargs.h"
+#include "kernels.h"
+#include "qxtn.h"
+
+namespace qx {
+
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ QxCplx cmul_acc(QxCplx acc, QxCplx a, QxCplx b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Operand tile loader shared by the matrix-product kernels.  A tile is ROWS
+// rows x 16 k of complex64; every chunk is 8 consecutive k of one row.  For a
+// k-contiguous operand a thread reads its chunk with 16-byte loads; otherwise
+// consecutive lanes take consecutive rows, so a row-contiguous operand is read
+// with coalesced 8-byte loads.  Row offsets are fixed per thread for the whole
+// kernel; the k offset of the tile origin is recomputed per k tile.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t scatter_bits(int64_t v, const int64_t* st, int n) {
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i)
+    if ((v >> i) & 1) off += st[i];
+  return off;
+}
+
+struct OperandView {
+  const QxCplx* X;
+  int64_t rows, K;
+  int64_t ld_r, ld_k;        // linear mode
+  const int64_t *rs, *ks;    // bit mode
+  int nr, nk;
+  bool bits, kc, vec;
+};
+
+template <int ROWS, bool KC>
+struct TileLoader {
+  static constexpr int BK = 16;
+  static constexpr int CH = ROWS * (BK / 8);
+  static constexpr int P = (CH + 255) / 256;
+  int64_t roff[P];           // offset of the chunk's row
+  int64_t kgoff[P];          // offset of the chunk's first k within the tile
+  int rloc[P], kgl[P];
+  bool rok[P];
+  __device__ static inline void row_kg(int c, int& r, int& kg) {
+    r = KC ? c / (BK / 8) : c % ROWS;
+    kg = KC ? c % (BK / 8) : c / ROWS;
+  }
+  __device__ inline int64_t koff(const OperandView& v, int64_t k) const {
+    return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
+  }
+  __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
+    const int64_t rbase = v.bits ? scatter_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
+#pragma unroll
+    for (int ps = 0; ps < P; ++ps) {
+      const int c = tid + ps * 256;
+      int r = 0, kg = 0;
+      if (c < CH) row_kg(c, r, kg);
+      rloc[ps] = r;
+      kgl[ps] = kg;
+      rok[ps] = c < CH && r0 + r < v.rows;
+      roff[ps] = rbase + (v.bits ? scatter_bits(r, v.rs, v.nr) : (int64_t)r * v.ld_r);
+      kgoff[ps] = koff(v, kg * 8);
+    }
+  }
+  // offset of k0 (a multiple of 16): bits 4 and up
+  __device__ inline int64_t kbase(const OperandView& v, int64_t k0) const { return koff(v, k0); }
+  __device__ inline void load(const OperandView& v, int64_t k0, QxCplx (&reg)[P][8]) const {
+    const int64_t kb0 = kbase(v, k0);
+#pragma unroll
+    for (int ps = 0; ps < P; ++ps) {
+      const int64_t kb = k0 + kgl[ps] * 8;
+      const QxCplx* src = v.X + roff[ps] + kb0 + kgoff[ps];
+      if (KC && v.vec && rok[ps] && kb + 8 <= v.K) {
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          v4f x = *(const v4f*)(src + j);
+          reg[ps][j] = {x[0], x[1]};
+          reg[ps][j + 1] = {x[2], x[3]};
+        }
+      } else if (KC) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[j] : QxCplx{0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t jo = v.bits ? ((j & 1) ? v.ks[0] : 0) + ((j & 2) ? v.ks[1] : 0) + ((j & 4) ? v.ks[2] : 0)
+                                    : (int64_t)j * v.ld_k;
+          reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[jo] : QxCplx{0.f, 0.f};
+        }
+      }
+    }
+  }
+};
+
+__device__ inline OperandView view_a(const GemmArgs& p, const QxCplx* X) {
+  OperandView v;
+  v.X = X; v.rows = p.M; v.K = p.K; v.ld_r = p.a_ms; v.ld_k = p.a_ks; v.rs = p.a_rs; v.ks = p.a_kst;
+  v.nr = p.nm; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.a_kc != 0 : p.a_ks == 1; v.vec = p.vec_a != 0;
+  return v;
+}
+__device__ inline OperandView view_b(const GemmArgs& p, const QxCplx* X) {
+  OperandView v;
+  v.X = X; v.rows = p.N; v.K = p.K; v.ld_r = p.b_ns; v.ld_k = p.b_ks; v.rs = p.b_rs; v.ks = p.b_kst;
+  v.nr = p.nn; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.b_kc != 0 : p.b_ks == 1; v.vec = p.vec_b != 0;
+  return v;
+}
+
+// Output offset of (m, n): m0 / n0 are tile origins, lm / ln offsets inside the tile.
+struct OutMap {
+  int64_t mbase, nbase;
+  __device__ inline int64_t m(const GemmArgs& p, int64_t lm) const {
+    return p.bits ? mbase + scatter_bits(lm, p.c_mst, p.nm) : mbase + lm * p.c_ms;
+  }
+  __device__ inline int64_t n(const GemmArgs& p, int64_t ln) const {
+    return p.bits ? nbase + scatter_bits(ln, p.c_nst, p.nn) : nbase + ln;
+  }
+};
+__device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
+  OutMap o;
+  o.mbase = p.bits ? scatter_bits(m0, p.c_mst, p.nm) : m0 * p.c_ms;
+  o.nbase = p.bits ? scatter_bits(n0, p.c_nst, p.nn) : n0;
+  return o;
+}
+
+// Work-group -> (batch item, hyper index, tile) with an XCD-aware order:
+// hardware deals work-groups round-robin over the 8 XCDs, so each XCD gets a
+// contiguous run of logical tiles and neighbours share its L2.
+struct TileCoord {
+  int item;
+  int64_t tm, tn, aoff, boff, coff;
+};
+__device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
+  const int64_t tiles_n = (p.N + BN - 1) / BN;
+  const int64_t tiles = ((p.M + BM - 1) / BM) * tiles_n;
+  const int64_t nwg = (int64_t)gridDim.x;
+  int64_t w = blockIdx.x;
+  const int64_t per = nwg / 8;
+  if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
+  const int64_t z = w / tiles, t = w % tiles;
+  TileCoord tc;
+  tc.tm = t / tiles_n;
+  tc.tn = t % tiles_n;
+  tc.item = (int)(z >> p.nh);
+  const int64_t h = z & ((1LL << p.nh) - 1);
+  tc.aoff = (int64_t)tc.item * p.a_item + (p.a_gather ? p.a_gather[tc.item] : 0);
+  tc.boff = (int64_t)tc.item * p.b_item + (p.b_gather ? p.b_gather[tc.item] : 0);
+  tc.coff = (int64_t)tc.item * p.c_item;
+#pragma unroll
+  for (int i = 0; i < QX_MAX_HBITS; ++i)
+    if (i < p.nh && ((h >> i) & 1)) { tc.aoff += p.a_hs[i]; tc.boff += p.b_hs[i]; tc.coff += p.c_hs[i]; }
+  return tc;
+}
+
+// Epilogue: each 32x32 accumulator block goes through LDS and is stored in the
+// order of ascending output address, so the stores form contiguous runs for
+// any output index order.  Element e of a block (10 bits, ordered by output
+// stride) is split into a lane part (bits 0..5) and a store-step part (bits
+// 6..9); both offsets are sums of precomputed per-bit strides.
+// stage: per-wave LDS area of 32 x 33 complex.
+template <int FM, int FN, int WM, int WN, bool UNROLL>
+__device__ inline void store_blocks(const GemmArgs& p, QxCplx* __restrict__ C, const OutMap& om, int64_t m0,
+                                    int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
+                                    const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
+  const int lrow = lane & 31, g = lane >> 5;
+  int lm_lane = 0, ln_lane = 0;
+  int64_t off_lane = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if ((lane >> b) & 1) {
+      lm_lane += p.ep_lm[b];
+      ln_lane += p.ep_ln[b];
+      off_lane += p.ep_st[b];
+    }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        stage[(8 * (i / 4) + 4 * g + (i % 4)) * 33 + lrow] = QxCplx{cr[a][b][i] * scale, ci[a][b][i] * scale};
+      __syncthreads();
+      const int64_t lm0 = wm * WM + a * 32, ln0 = wn * WN + b * 32;
+      QxCplx* __restrict__ Cb = C + om.m(p, lm0) + om.n(p, ln0) + off_lane;
+      auto put = [&](int j) {
+        int lm = lm_lane, ln = ln_lane;
+        int64_t off = 0;
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2)
+          if ((j >> b2) & 1) {
+            lm += p.ep_lm[6 + b2];
+            ln += p.ep_ln[6 + b2];
+            off += p.ep_st[6 + b2];
+          }
+        if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) Cb[off] = stage[lm * 33 + ln];
+      };
+      // a rolled loop keeps the FP32 kernel's registers low enough for two waves per SIMD
+      if (UNROLL) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) put(j);
+      } else {
+#pragma unroll 1
+        for (int j = 0; j < 16; ++j) put(j);
+      }
+    }
+}
+
+}  // namespace qx

@@ -24,6 +24,12 @@ struct QxCplx { float x, y; };
 struct SimtArgs {
   const QxCplx *a, *b;
   QxCplx *c;
+  // fixed sliced indices of leaf operands: offset += bit j of the block's first
+  // slice (block[0]) times stride
+  const int64_t *block;
+  int32_t nfix_a, nfix_b;
+  int32_t fix_ja[4], fix_jb[4];
+  int64_t fix_sa[4], fix_sb[4];
   int64_t a_item, b_item, c_item;        // item strides (0 = operand shared by all items)
   const int64_t *a_gather, *b_gather;    // per-item offsets, or null
   int32_t n_out, n_k, n_items;
@@ -95,6 +101,7 @@ struct PermArgs {
 //   amp[item] += sum_{s in [s_lo, s_hi)} root[item-offset + sum_j bit_j(s) * s_stride[j]]
 struct SliceSumArgs {
   const QxCplx *root;
+  const int64_t *block;                 // if set, the slice range is block[1], block[2]
   int64_t root_item;
   const int64_t *root_gather;
   double *amp;                          // [items][2]
@@ -113,6 +120,17 @@ struct AbsmaxArgs {
   float *partial;                       // [gridDim.x]
   unsigned int *ticket;                 // zero before the first launch; left zero after each
   float *scale;
+};
+
+// Slice-block state kept on the device so one captured block program can be
+// replayed for every block:  state[0] first slice of the current block,
+// state[1], state[2] local slice range [lo, hi), state[3] next block index,
+// state[4], state[5] the call's slice range, state[6] log2 slices per block.
+struct BlockArgs {
+  int64_t *state;
+  double *acc;                          // [n_items][2] FP64 accumulator (zeroed by k_block_init)
+  int64_t first_block, slice_begin, slice_end;
+  int32_t js, n_items;
 };
 
 // Per-bitstring gather offsets: out[item] = sum_j bit_{q_j}(x[item]) * stride_j

@@ -5,16 +5,38 @@
 
 namespace qx {
 
-enum GemmTile { GEMM_TILE_128x128 = 0, GEMM_TILE_64x64 = 1 };
+// Work-group tile shapes of the matrix-core GEMMs (4 waves in a 2x2 grid).
+enum GemmTile {
+  GEMM_TILE_128x128 = 0,
+  GEMM_TILE_64x64 = 1,
+  GEMM_TILE_128x64 = 2,
+  GEMM_TILE_64x128 = 3,
+  GEMM_TILE_256x128 = 4,
+  GEMM_TILE_128x256 = 5,
+  GEMM_N_TILES = 6
+};
+inline void gemm_tile_dims(int tile, int& bm, int& bn) {
+  static const int d[GEMM_N_TILES][2] = {{128, 128}, {64, 64}, {128, 64}, {64, 128}, {256, 128}, {128, 256}};
+  bm = d[tile][0];
+  bn = d[tile][1];
+}
+// Default tile for a product of the given sizes (used without autotuning).
+int gemm_default_tile(int64_t M, int64_t N);
 
 hipError_t launch_simt(const SimtArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, int precision, int tile, hipStream_t s);
+hipError_t launch_gemm_c64(const GemmArgs& a, int tile, hipStream_t s);
+hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s);
+hipError_t launch_gemm_fp16(const GemmArgs& a, int tile, hipStream_t s);
 hipError_t launch_dot(const DotArgs& a, hipStream_t s);
 void permute_setup(PermArgs& a);
 void gemm_epilogue_setup(GemmArgs& g);  // fills ep_bit from the output strides  // fills the tile / outer-bit fields from rank and in_pos
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+hipError_t launch_block_init(const BlockArgs& a, hipStream_t s);
+hipError_t launch_block_advance(const BlockArgs& a, hipStream_t s);
+hipError_t launch_block_finish(const BlockArgs& a, double* amp, hipStream_t s);
 hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s);  // grid <= 1024 work-groups
 constexpr int ABSMAX_PARTIALS = 1024;
 

@@ -443,7 +443,7 @@ struct Compiler {
       }
     }
     op.flops = 8.0 * (double)g.M * g.N * g.K * std::ldexp(1.0, g.nh) * items;
-    op.tile = (g.M >= 128 && g.N >= 128) ? 0 : 1;
+    op.tile = gemm_default_tile(g.M, g.N);
   }
 
   bool emit_node(int p) {

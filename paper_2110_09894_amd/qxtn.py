@@ -50,7 +50,7 @@ class _Network(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_bitstrings", C.c_int32),
                 ("slice_batch_log2", C.c_int32), ("dry_run", C.c_int32),
-                ("hbm_budget_bytes", C.c_int64)]
+                ("hbm_budget_bytes", C.c_int64), ("autotune", C.c_int32), ("eager", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -132,7 +132,7 @@ class Plan:
     """Owns a qx_plan handle (qx_plan_create / qx_plan_destroy)."""
 
     def __init__(self, network, tree, sliced=(), precision="c64", max_bitstrings=1, slice_batch_log2=-1,
-                 dry_run=False, hbm_budget_bytes=0, stream=None):
+                 dry_run=False, hbm_budget_bytes=0, autotune=False, eager=False, stream=None):
         index_ptr, index_ids, data_ptr, data, output_index = network.to_csr()
         self._keep = [np.ascontiguousarray(index_ptr, np.int64), np.ascontiguousarray(index_ids, np.int64),
                       np.ascontiguousarray(data_ptr, np.int64), np.ascontiguousarray(data, np.float64),
@@ -143,7 +143,8 @@ class Plan:
         tr = np.ascontiguousarray(np.asarray(tree, dtype=np.int32).reshape(-1))
         sl = np.ascontiguousarray(np.asarray(list(sliced), dtype=np.int64))
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        opt = _Options(prec, int(max_bitstrings), int(slice_batch_log2), int(bool(dry_run)), int(hbm_budget_bytes))
+        opt = _Options(prec, int(max_bitstrings), int(slice_batch_log2), int(bool(dry_run)), int(hbm_budget_bytes),
+                       int(bool(autotune)), int(bool(eager)))
         h = C.c_void_p()
         _check(lib().qx_plan_create(C.byref(net), _ptr(tr, C.c_int32) if tr.size else None,
                                     _ptr(sl, C.c_int64) if sl.size else None, len(sl), C.byref(opt),

@@ -210,3 +210,36 @@ def test_mirror_circuit_split_bf16():
     got = gpu_amplitudes(plan, xs)
     assert abs(got[0] - 1) < 1e-4
     assert np.max(np.abs(got[1:])) < 1e-4
+
+
+def test_graph_replays_match_eager_bitwise():
+    """The captured block program, replayed for every block of several calls with
+    eager work in between, gives bitwise the same amplitudes as per-op launches."""
+    circ = random_grid_circuit(4, 4, 8, 33)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=5)
+    sl = tree_trimming(net, tree, 6, seed=5)
+    xs = random_bitstrings(16, 12, 8)
+    eager = qxtn.Plan(net, tree, sl, max_bitstrings=16, slice_batch_log2=2, eager=True)
+    graph = qxtn.Plan(net, tree, sl, max_bitstrings=16, slice_batch_log2=2)
+    want = gpu_amplitudes(eager, xs)
+    for rep in range(3):
+        got = gpu_amplitudes(graph, xs)
+        assert np.array_equal(got.view(np.float64), want.view(np.float64)), rep
+        torch.ones(1024, device="cuda").sum().item()  # unrelated eager work between replays
+        # a different batch size captures and replays its own graph
+        got5 = gpu_amplitudes(graph, xs[:5], (3, 60))
+        want5 = gpu_amplitudes(eager, xs[:5], (3, 60))
+        assert np.array_equal(got5.view(np.float64), want5.view(np.float64)), rep
+    assert rms_err(want, oracle.amplitudes_statevector(circ, xs)) < TOL_C64
+
+
+def test_autotuned_plan_matches_oracle():
+    w = configs.get("c2")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs()
+    xs = w.bitstrings()
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), autotune=True)
+    got = gpu_amplitudes(plan, xs, (777, 778))
+    want = np.array([oracle.contract_slice(net, tree, x, sl, 777) for x in xs])
+    assert rms_err(got, want) < TOL_C64

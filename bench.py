@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket launches with events")
+    ap.add_argument("--no-autotune", action="store_true", help="default tile shapes instead of timed ones")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison run")
+    ap.add_argument("--no-permute", action="store_true", help="skip the standalone permute measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -90,43 +93,62 @@ def main():
     B = len(xs)
     net = w.network()
     torch.cuda.set_device(0)
-    plan = qxtn.Plan(net, tree, sliced, precision=args.precision, max_bitstrings=B)
-    info = plan.info()
     x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
-    amp = torch.zeros((B, 2), dtype=torch.float64, device="cuda")
     n_slices = 1 << len(sliced)
 
-    for _ in range(args.warmup):
-        plan.contract(x, amp)
-    torch.cuda.synchronize()
-    if not args.no_timing:
-        plan.set_timing(True)
-        plan.get_timing(reset=True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record()
-        plan.contract(x, amp)
-        ends[i].record()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timing = plan.get_timing(reset=True) if not args.no_timing else None
-    plan.set_timing(False) if not args.no_timing else None
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    def run(precision):
+        """Plan, warm up, then time exactly args.steps full contractions."""
+        plan = qxtn.Plan(net, tree, sliced, precision=precision, max_bitstrings=B,
+                         autotune=not args.no_autotune)
+        info = plan.info()
+        amp = torch.zeros((B, 2), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            plan.contract(x, amp)
+        torch.cuda.synchronize()
+        if not args.no_timing:
+            plan.set_timing(True)
+            plan.get_timing(reset=True)
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            starts[i].record()
+            plan.contract(x, amp)
+            ends[i].record()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timing = None
+        if not args.no_timing:
+            timing = plan.get_timing(reset=True)
+            plan.set_timing(False)
+        lat = np.array([s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)])
+        executed = info["flops_block"] * (n_slices >> info["slice_batch_log2"]) + info["flops_call"]
+        r = {"value": B * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+             "complex_tflops": executed / (elapsed / args.steps) / 1e12,
+             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+             "slice_batch": 1 << info["slice_batch_log2"]}
+        if timing is not None:
+            g = timing["gemm"]
+            ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
+            r["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
+                             "unit": "TFLOP/s", "frac": ach / PEAKS[precision], "traffic": None,
+                             "kernel": "k_gemm_f32" if precision == "c64" else "k_gemm_split",
+                             "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
+                             "launches_per_step": g["launches"] / args.steps,
+                             "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}
+            r["time_by_class_ms_per_step"] = {k: 1e3 * v["seconds"] / args.steps for k, v in timing.items()}
+        return plan, r
 
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = B * args.steps / elapsed
-    executed = info["flops_block"] * (n_slices >> info["slice_batch_log2"]) + info["flops_call"]
+    plan, main = run(args.precision)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main["value"],
         "unit": "amplitudes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -134,37 +156,63 @@ def main():
         "data": "synthetic (seeded random circuit, planner and bitstrings; no external dataset)",
         "config": {"workload": f"{w.name}: {w.description}", "precision": args.precision,
                    "qubits": w.n_qubits, "depth": w.depth, "slices": n_slices, "bitstrings": B,
-                   "slice_batch": 1 << info["slice_batch_log2"], "tree_width": st["width"],
+                   "slice_batch": main["slice_batch"], "tree_width": st["width"],
                    "flops_per_slice_amplitude": st["flops_per_slice"]},
-        "complex_tflops": executed / (elapsed / args.steps) / 1e12,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "complex_tflops": main["complex_tflops"],
+        "latency_ms": main["latency_ms"],
     }
-    if timing is not None:
-        g = timing["gemm"]
-        ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
-        out["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[args.precision] / 1e12,
-                           "unit": "TFLOP/s", "frac": ach / PEAKS[args.precision], "traffic": None,
-                           "kernel": "k_gemm_f32" if args.precision == "c64" else "k_gemm_split",
-                           "mfma_util": ach * (1 if args.precision == "c64" else 3) / PEAKS[args.precision],
-                           "launches_per_step": g["launches"] / args.steps,
-                           "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}
-        out["time_by_class_ms_per_step"] = {k: 1e3 * v["seconds"] / args.steps for k, v in timing.items()}
-        pm = timing["permute"]
-        out["permute_gbs"] = pm["bytes"] / pm["seconds"] / 1e9 if pm["seconds"] > 0 else None
+    for k in ("roofline", "time_by_class_ms_per_step"):
+        if k in main:
+            out[k] = main[k]
+    split_plans = {}
+    if args.precision == "c64" and not args.no_split:
+        for prec in ("split_bf16",):
+            sp, r = run(prec)
+            split_plans[prec] = sp
+            r["speedup_vs_c64"] = r["value"] / main["value"]
+            out[prec] = r
+
+    # index-permute primitive on its own (the workload's plan needs none): HBM roofline
+    if not args.no_permute:
+        rank = 26
+        rng = np.random.default_rng(7)
+        in_pos = rng.permutation(rank).astype(np.int32)
+        src = torch.randn(2 << rank, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        qxtn.permute_c64(src, dst, in_pos, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            qxtn.permute_c64(src, dst, in_pos, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        gbs = 16.0 * (1 << rank) / sec / 1e9
+        out["permute"] = {"kernel": "k_permute", "elements": 1 << rank, "avg_launch_ms": sec * 1e3,
+                          "achieved_gbs": gbs, "frac_of_hbm_peak": gbs * 1e9 / HBM_PEAK,
+                          "in_pos_seed": 7}
+        del src, dst
 
     # accuracy on slice 0 and the CPU baseline share the oracle sample
     if not args.no_cpu_baseline:
         cb, ref = cpu_baseline(w, tree, sliced, xs, args.cpu_seconds)
         out["cpu_baseline"] = cb
         k = len(ref)
-        a0 = torch.zeros((k, 2), dtype=torch.float64, device="cuda")
-        plan.contract(x[:k], a0, (0, 1))
-        torch.cuda.synchronize()
-        got = a0.cpu().numpy()
-        got = got[:, 0] + 1j * got[:, 1]
         scale = np.sqrt(np.mean(np.abs(ref) ** 2))
-        out["error_vs_oracle"] = {"slice": 0, "bitstrings": k,
-                                  "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
+
+        def err(pl):
+            a0 = torch.zeros((k, 2), dtype=torch.float64, device="cuda")
+            pl.contract(x[:k], a0, (0, 1))
+            torch.cuda.synchronize()
+            got = a0.cpu().numpy()
+            got = got[:, 0] + 1j * got[:, 1]
+            return {"slice": 0, "bitstrings": k, "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
+
+        out["error_vs_oracle"] = err(plan)
+        for prec, sp in split_plans.items():
+            out[prec]["error_vs_oracle"] = err(sp)
     print(json.dumps(out), flush=True)
 
 

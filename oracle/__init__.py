@@ -15,6 +15,8 @@ Three independent computations of one definition, all in complex128:
   by the bitstring (Eq. 1 with the output closure of Sec. II).
 * ``tree_contract`` (O3) -- pairwise contraction along a given tree
   (Sec. III-A) of each slice's network, slices summed (Eq. 2).
+* ``sampling`` -- empirical-supremum rejection sampling (Sec. III-B) from the
+  exact O1 probabilities.
 
 Every function here is pinned by tests against closed forms, invariants and the
 other two computations; none is "parity unpinned".
@@ -22,6 +24,8 @@ other two computations; none is "parity unpinned".
 from .statevector import statevector, amplitudes_statevector
 from .bruteforce import amplitude_bruteforce
 from .tree_contract import contract_slice, amplitude_sliced, amplitudes_sliced, slice_values
+from .sampling import probabilities, empirical_supremum_sample
 
 __all__ = ["statevector", "amplitudes_statevector", "amplitude_bruteforce", "contract_slice",
-           "amplitude_sliced", "amplitudes_sliced", "slice_values"]
+           "amplitude_sliced", "amplitudes_sliced", "slice_values", "probabilities",
+           "empirical_supremum_sample"]

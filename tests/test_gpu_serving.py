@@ -1,0 +1,113 @@
+"""Serving: continuous batching over resident plans (GPU).  Every request's result
+is bitwise the same alone and in a mix, and matches the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2110_09894_amd import qxtn  # noqa: E402
+from paper_2110_09894_amd.serve import Server, AdmissionError  # noqa: E402
+from paper_2110_09894_amd.sampling import rejection_sample  # noqa: E402
+from workloads import (circuit_to_network, random_grid_circuit, ghz_circuit, greedy_tree,  # noqa: E402
+                       tree_trimming, random_bitstrings, sampling_inputs)
+from tests._util import rms_err, gpu_amplitudes  # noqa: E402
+
+
+def _circuits():
+    out = {}
+    c1 = random_grid_circuit(3, 4, 8, 71)
+    n1 = circuit_to_network(c1)
+    out["g12"] = (c1, n1, greedy_tree(n1, seed=1), [])
+    c2 = random_grid_circuit(4, 4, 10, 72)
+    n2 = circuit_to_network(c2)
+    t2 = greedy_tree(n2, seed=2)
+    out["g16"] = (c2, n2, t2, tree_trimming(n2, t2, 4, seed=2))
+    c3 = ghz_circuit(20)
+    n3 = circuit_to_network(c3)
+    out["ghz20"] = (c3, n3, greedy_tree(n3), [])
+    return out
+
+
+def _server(circs, **kw):
+    srv = Server(**kw)
+    for name, (_, net, tree, sl) in circs.items():
+        srv.register(name, net, tree, sl, max_bitstrings=64)
+    srv.start()
+    return srv
+
+
+def test_mix_equals_alone_and_oracle():
+    circs = _circuits()
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(24):
+        name = ["g12", "g16", "ghz20"][i % 3]
+        n = circs[name][0].n_qubits
+        reqs.append((name, random_bitstrings(n, int(rng.integers(1, 150)), 100 + i)))
+    srv = _server(circs, max_replicas=2)
+    futs = [srv.submit_amplitudes(name, xs) for name, xs in reqs]
+    mixed = [f.result(timeout=120) for f in futs]
+    st = srv.stats()
+    srv.stop()
+    assert st["completed_amplitudes"] == sum(len(x) for _, x in reqs)
+    assert st["max_concurrency"] >= 2
+    srv1 = _server(circs, max_replicas=1)
+    for (name, xs), got in zip(reqs, mixed):
+        alone = srv1.submit_amplitudes(name, xs).result(timeout=120)
+        assert np.array_equal(alone.view(np.float64), got.view(np.float64)), name
+        want = oracle.amplitudes_statevector(circs[name][0], xs)
+        assert rms_err(got, want) < 1e-5
+    srv1.stop()
+
+
+def test_admission_by_budget_and_unknown_circuit():
+    circs = _circuits()
+    srv = Server(hbm_budget_bytes=1 << 10)
+    with pytest.raises(AdmissionError):
+        srv.register("g16", circs["g16"][1], circs["g16"][2], circs["g16"][3], max_bitstrings=64)
+    srv = _server({"g12": circs["g12"]})
+    f = srv.submit_amplitudes("nope", np.zeros(3, np.uint64))
+    with pytest.raises(AdmissionError):
+        f.result(timeout=10)
+    assert srv.stats()["rejected"] == 1
+    srv.stop()
+
+
+def test_eviction_under_tight_budget():
+    circs = _circuits()
+    need = max(Server().register(n, c[1], c[2], c[3], max_bitstrings=64) for n, c in circs.items())
+    srv = Server(hbm_budget_bytes=need + 1024, max_replicas=1)
+    for name, (_, net, tree, sl) in circs.items():
+        srv.register(name, net, tree, sl, max_bitstrings=64)
+    srv.start()
+    outs = [(name, srv.submit_amplitudes(name, random_bitstrings(circs[name][0].n_qubits, 10, 7)))
+            for name in ["g12", "g16", "ghz20", "g12"]]
+    for name, f in outs:
+        got = f.result(timeout=120)
+        xs = random_bitstrings(circs[name][0].n_qubits, 10, 7)
+        assert rms_err(got, oracle.amplitudes_statevector(circs[name][0], xs)) < 1e-5
+    assert srv.stats()["resident_bytes"] <= need + 1024
+    srv.stop()
+
+
+def test_sampling_request_matches_direct_sampler_and_oracle():
+    circs = _circuits()
+    circ, net, tree, sl = circs["g12"]
+    cand, u = sampling_inputs(12, 3000, 11)
+    srv = _server({"g12": circs["g12"]})
+    samples, info = srv.submit_sample("g12", 200, cand, u, warmup=32, batch=64).result(timeout=120)
+    srv.stop()
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=64)
+    direct, dinfo = rejection_sample(lambda c: gpu_amplitudes(plan, c), 12, cand, u, 200, warmup=32, batch=64)
+    assert np.array_equal(samples, direct)
+    # against exact probabilities: every decision whose margin exceeds the amplitude error agrees
+    probs = oracle.probabilities(circ)
+    want, dec = oracle.empirical_supremum_sample(probs, 12, cand, u, 200, warmup=32)
+    n = min(len(dec), len(dinfo["decisions"]))
+    mismatch = np.nonzero(dinfo["decisions"][:n] != dec[:n])[0]
+    assert len(mismatch) <= 2, mismatch
+    if len(mismatch) == 0:
+        assert np.array_equal(samples, want)

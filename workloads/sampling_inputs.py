@@ -1,0 +1,13 @@
+"""Random inputs of the rejection sampler: uniform candidate bitstrings and one
+uniform variate per candidate, from numpy.random.Generator(PCG64(seed))."""
+from __future__ import annotations
+
+import numpy as np
+
+from .bitstrings import random_bitstrings
+
+
+def sampling_inputs(n_qubits: int, count: int, seed: int):
+    cand = random_bitstrings(n_qubits, count, seed)
+    u = np.random.Generator(np.random.PCG64(seed + 7919)).random(count)
+    return cand, u

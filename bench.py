@@ -63,6 +63,62 @@ def cpu_baseline(w, tree, sliced, xs, seconds):
     }, np.array(vals)
 
 
+def serve_bench(args):
+    """c5: saturation probe (all requests at once), then Poisson arrivals at 70% of it."""
+    import torch
+    from paper_2110_09894_amd.serve import Server
+    from workloads.configs import SERVING
+
+    torch.cuda.set_device(0)
+    mix = SERVING
+    circs = mix.circuits()
+    srv = Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_replicas=2)
+    for name, circ, net, tree, sliced, st in circs:
+        srv.register(name, net, tree, sliced, precision=args.precision, max_bitstrings=mix.max_bitstrings,
+                     autotune=not args.no_autotune)
+    srv.start()
+    # warm-up: one request per circuit creates its plan (and tunes its tiles)
+    for name, circ, *_ in circs:
+        srv.submit_amplitudes(name, np.zeros(mix.max_bitstrings, np.uint64)).result()
+    names = [c[0] for c in circs]
+
+    def run(reqs, rate):
+        srv.latencies.clear()
+        t0 = time.monotonic()
+        futs = []
+        for off, which, xs in reqs:
+            if rate:
+                delay = t0 + off / rate - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+            futs.append(srv.submit_amplitudes(names[which], xs))
+        for f in futs:
+            f.result()
+        el = time.monotonic() - t0
+        lat = np.array(srv.latencies)
+        return {"requests": len(reqs), "amplitudes": int(sum(len(x) for _, _, x in reqs)), "seconds": el,
+                "amplitudes_per_s": sum(len(x) for _, _, x in reqs) / el, "requests_per_s": len(reqs) / el,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+    sat = run(mix.requests(args.serve_probe), None)
+    rate = 0.7 * sat["requests_per_s"]
+    reqs = mix.requests(args.serve_probe + args.serve_requests)[args.serve_probe:]
+    base = reqs[0][0]
+    reqs = [(t - base, w, x) for t, w, x in reqs]
+    pois = run(reqs, rate)
+    st = srv.stats()
+    srv.stop()
+    out = {"metric": "amplitudes/s; p50/p99 latency (serving mix)", "value": pois["amplitudes_per_s"],
+           "unit": "amplitudes/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+           "dtype": DTYPES[args.precision], "data": "synthetic (seeded circuits, Poisson arrivals, bitstrings)",
+           "config": {"workload": f"{mix.name}: {mix.description}", "arrival_rate_per_s": rate,
+                      "max_bitstrings_per_call": mix.max_bitstrings, "hbm_budget_gib": args.serve_budget_gib},
+           "latency_ms": {"p50": pois["p50_ms"], "p99": pois["p99_ms"]},
+           "poisson": pois, "saturation": sat, "max_concurrency": st["max_concurrency"],
+           "rejected": st["rejected"], "resident_gib": st["resident_bytes"] / 2 ** 30}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,12 +132,19 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default tile shapes instead of timed ones")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison run")
     ap.add_argument("--no-permute", action="store_true", help="skip the standalone permute measurement")
+    ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
+    ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
+    ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(slices shard across GPUs by contiguous ranges, but no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c5":
+        serve_bench(args)
+        return
 
     import torch
     from paper_2110_09894_amd import qxtn

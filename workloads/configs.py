@@ -70,3 +70,45 @@ CONFIGS = {
 
 def get(name: str) -> Workload:
     return CONFIGS[name]
+
+
+@dataclass
+class ServingMix:
+    """Poisson stream of amplitude requests over a pool of resident circuits."""
+    name: str
+    pool: list            # (rows, cols, depth, circuit_seed, n_sliced)
+    max_bitstrings: int
+    request_max_bitstrings: int
+    seed: int
+    planner_trials: int = 8
+    description: str = ""
+
+    def circuits(self):
+        out = []
+        for rows, cols, depth, cseed, k in self.pool:
+            circ = random_grid_circuit(rows, cols, depth, cseed)
+            net = circuit_to_network(circ)
+            tree, sliced, st = plan_network(net, k, trials=self.planner_trials, seed=cseed + 7)
+            out.append((f"{rows}x{cols}_d{depth}", circ, net, tree, sliced, st))
+        return out
+
+    def requests(self, count: int):
+        """(arrival offset in units of 1/rate, circuit index, bitstrings) for ``count`` requests."""
+        rng = np.random.Generator(np.random.PCG64(self.seed))
+        gaps = rng.exponential(1.0, size=count)
+        which = rng.integers(0, len(self.pool), size=count)
+        sizes = rng.integers(1, self.request_max_bitstrings + 1, size=count)
+        out, t = [], 0.0
+        for i in range(count):
+            t += gaps[i]
+            rows, cols = self.pool[which[i]][0], self.pool[which[i]][1]
+            xs = random_bitstrings(rows * cols, int(sizes[i]), self.seed * 1000 + i)
+            out.append((t, int(which[i]), xs))
+        return out
+
+
+SERVING = ServingMix(
+    "c5", pool=[(4, 5, 8, 51, 0), (4, 5, 14, 52, 0), (5, 6, 8, 53, 0), (5, 6, 10, 54, 2), (7, 7, 8, 55, 4)],
+    max_bitstrings=256, request_max_bitstrings=1024, seed=5,
+    description="Poisson amplitude requests of 1-1024 bitstrings over 20-, 30- and 49-qubit grids "
+                "(4x5 d8, 4x5 d14, 5x6 d8, 5x6 d10, 7x7 d8), plans resident, admitted by HBM budget")

@@ -119,6 +119,43 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def c4_bench(args):
+    """c4: a contiguous block of slices of the 49-qubit network for one bitstring."""
+    import torch
+    from paper_2110_09894_amd import qxtn
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    w = configs.get("c4")
+    tree, sliced, st = w.plan_inputs()
+    xs = w.bitstrings()
+    x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
+    plan = qxtn.Plan(w.network(), tree, sliced, precision=args.precision, max_bitstrings=1,
+                     autotune=not args.no_autotune)
+    info = plan.info()
+    bsz = 1 << info["slice_batch_log2"]
+    n = max(bsz, (args.slices // bsz) * bsz)
+    amp = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    plan.contract(x, amp, (0, bsz))  # warm-up: one block (captures the block program)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.contract(x, amp, (0, n))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    flops = info["flops_block"] * (n // bsz) + info["flops_call"]
+    total = 1 << len(sliced)
+    out = {"metric": "slices/s + complex TFLOP/s (49-qubit block)", "value": n / el, "unit": "slices/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": DTYPES[args.precision],
+           "data": "synthetic (seeded circuit and bitstring)",
+           "config": {"workload": f"c4: {w.description}", "slices_timed": n, "slice_batch": bsz,
+                      "tree_width": st["width"], "flops_per_slice": st["flops_per_slice"]},
+           "seconds": el, "complex_tflops": flops / el / 1e12,
+           "frac_of_peak": flops / el / PEAKS[args.precision],
+           "extrapolated_seconds_per_amplitude": el * total / n,
+           "extrapolation_note": f"x{total // n} to all 2^{len(sliced)} slices"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +169,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default tile shapes instead of timed ones")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison run")
     ap.add_argument("--no-permute", action="store_true", help="skip the standalone permute measurement")
+    ap.add_argument("--slices", type=int, default=4096, help="c4: contiguous slices timed")
     ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
     ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
@@ -144,6 +182,9 @@ def main():
 
     if args.workload == "c5":
         serve_bench(args)
+        return
+    if args.workload == "c4":
+        c4_bench(args)
         return
 
     import torch

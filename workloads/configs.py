@@ -63,7 +63,7 @@ CONFIGS = {
                    description="12-qubit 3x4 grid, depth 8, no slicing, 64 bitstrings"),
     "c2": Workload("c2", 5, 6, 12, 2, 10, 256, 1002, 100, 40,
                    description="30-qubit 5x6 grid, depth 12, 10 sliced indices (1024 slices), 256 bitstrings"),
-    "c4": Workload("c4", 7, 7, 14, 4, 24, 1, 1004, 104, 16, width_cap=30,
+    "c4": Workload("c4", 7, 7, 14, 4, 24, 1, 1004, 104, 64, width_cap=30,
                    description="49-qubit 7x7 grid, depth 14, 24 sliced indices, 1 bitstring"),
 }
 

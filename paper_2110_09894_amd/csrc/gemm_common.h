@@ -35,6 +35,15 @@ __device__ inline int64_t scatter_bits(int64_t v, const int64_t* st, int n) {
   return off;
 }
 
+// k-contiguous loading (8 consecutive k values with 16-byte loads) needs the
+// operand's k stride to be 1 for k bits 0..2, 16-byte alignment and K % 8 == 0.
+__host__ __device__ inline bool gemm_a_kc(const GemmArgs& p) {
+  return (p.bits ? p.a_kc != 0 : p.a_ks == 1) && p.vec_a && p.K % 8 == 0;
+}
+__host__ __device__ inline bool gemm_b_kc(const GemmArgs& p) {
+  return (p.bits ? p.b_kc != 0 : p.b_ks == 1) && p.vec_b && p.K % 8 == 0;
+}
+
 struct OperandView {
   const QxCplx* X;
   int64_t rows, K;
@@ -76,28 +85,32 @@ struct TileLoader {
   }
   // offset of k0 (a multiple of 16): bits 4 and up
   __device__ inline int64_t kbase(const OperandView& v, int64_t k0) const { return koff(v, k0); }
+  // Branch-free: invalid rows read row 0 of the tile origin (a valid address) and
+  // are zeroed with selects, so the compiler can keep several tiles of loads in
+  // flight.  A k-contiguous operand is only used when the host has checked 16-byte
+  // alignment and K % 8 == 0; every other operand takes the row-contiguous path.
   __device__ inline void load(const OperandView& v, int64_t k0, QxCplx (&reg)[P][8]) const {
     const int64_t kb0 = kbase(v, k0);
 #pragma unroll
     for (int ps = 0; ps < P; ++ps) {
       const int64_t kb = k0 + kgl[ps] * 8;
-      const QxCplx* src = v.X + roff[ps] + kb0 + kgoff[ps];
-      if (KC && v.vec && rok[ps] && kb + 8 <= v.K) {
+      const bool ok = rok[ps];
+      const QxCplx* src = v.X + (ok ? roff[ps] : 0) + kb0 + kgoff[ps];
+      if (KC) {
 #pragma unroll
         for (int j = 0; j < 8; j += 2) {
-          v4f x = *(const v4f*)(src + j);
-          reg[ps][j] = {x[0], x[1]};
-          reg[ps][j + 1] = {x[2], x[3]};
+          const v4f x = *(const v4f*)(src + j);
+          reg[ps][j] = {ok ? x[0] : 0.f, ok ? x[1] : 0.f};
+          reg[ps][j + 1] = {ok ? x[2] : 0.f, ok ? x[3] : 0.f};
         }
-      } else if (KC) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[j] : QxCplx{0.f, 0.f};
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+          const bool okj = ok && kb + j < v.K;
           const int64_t jo = v.bits ? ((j & 1) ? v.ks[0] : 0) + ((j & 2) ? v.ks[1] : 0) + ((j & 4) ? v.ks[2] : 0)
                                     : (int64_t)j * v.ld_k;
-          reg[ps][j] = (rok[ps] && kb + j < v.K) ? src[jo] : QxCplx{0.f, 0.f};
+          const QxCplx x = src[okj ? jo : 0];
+          reg[ps][j] = {okj ? x.x : 0.f, okj ? x.y : 0.f};
         }
       }
     }
@@ -107,13 +120,13 @@ struct TileLoader {
 __device__ inline OperandView view_a(const GemmArgs& p, const QxCplx* X) {
   OperandView v;
   v.X = X; v.rows = p.M; v.K = p.K; v.ld_r = p.a_ms; v.ld_k = p.a_ks; v.rs = p.a_rs; v.ks = p.a_kst;
-  v.nr = p.nm; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.a_kc != 0 : p.a_ks == 1; v.vec = p.vec_a != 0;
+  v.nr = p.nm; v.nk = p.nk; v.bits = p.bits != 0; v.kc = gemm_a_kc(p); v.vec = p.vec_a != 0;
   return v;
 }
 __device__ inline OperandView view_b(const GemmArgs& p, const QxCplx* X) {
   OperandView v;
   v.X = X; v.rows = p.N; v.K = p.K; v.ld_r = p.b_ns; v.ld_k = p.b_ks; v.rs = p.b_rs; v.ks = p.b_kst;
-  v.nr = p.nn; v.nk = p.nk; v.bits = p.bits != 0; v.kc = p.bits ? p.b_kc != 0 : p.b_ks == 1; v.vec = p.vec_b != 0;
+  v.nr = p.nn; v.nk = p.nk; v.bits = p.bits != 0; v.kc = gemm_b_kc(p); v.vec = p.vec_b != 0;
   return v;
 }
 

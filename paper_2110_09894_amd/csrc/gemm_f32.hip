@@ -147,8 +147,7 @@ static hipError_t launch_f32(const GemmArgs& a, hipStream_t s) {
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
   if (nwg <= 0) return hipSuccess;
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool akc = a.bits ? a.a_kc != 0 : a.a_ks == 1;
-  const bool bkc = a.bits ? a.b_kc != 0 : a.b_ks == 1;
+  const bool akc = gemm_a_kc(a), bkc = gemm_b_kc(a);
   dim3 grid((unsigned)nwg), block(256);
   if (akc && bkc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, true>), grid, block, 0, s, a);
   else if (akc) hipLaunchKernelGGL((k_gemm_f32<BM, BN, true, false>), grid, block, 0, s, a);

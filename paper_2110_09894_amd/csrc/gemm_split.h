@@ -2,6 +2,8 @@
 #pragma once
 #include "gemm_common.h"
 
+#include <type_traits>
+
 namespace qx {
 
 // ---------------------------------------------------------------------------
@@ -66,10 +68,13 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
   LB lb;
   la.init(va, m0, tid);
   lb.init(vb, n0, tid);
-  QxCplx ra[LA::P][8], rb[LB::P][8];
-  auto load_tiles = [&](int64_t k0) {
-    la.load(va, k0, ra);
-    lb.load(vb, k0, rb);
+  // PF register sets: with two, tile t lives in set t & 1 and global loads run two
+  // k tiles ahead; the 256-wide tiles keep one set (two would spill)
+  constexpr int PF = (BM * BN > 128 * 128) ? 1 : 2;
+  QxCplx ra[PF][LA::P][8], rb[PF][LB::P][8];
+  auto load_tiles = [&](int64_t k0, auto set) {
+    la.load(va, k0, ra[decltype(set)::value % PF]);
+    lb.load(vb, k0, rb[decltype(set)::value % PF]);
   };
   // split 8 complex values into the four planes and store 16 bytes per plane
   auto split_store = [&](T* p0, T* p1, T* p2, T* p3, const QxCplx (&v)[8], float sc) {
@@ -88,7 +93,8 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
     *(V8*)p2 = ih;
     *(V8*)p3 = il;
   };
-  auto store_tiles = [&](int buf) {
+  auto store_tiles = [&](int buf, auto set) {
+    constexpr int S = decltype(set)::value;
 #pragma unroll
     for (int ps = 0; ps < LA::P; ++ps) {
       const int c = tid + ps * 256;
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
         int r, kg;
         LA::row_kg(c, r, kg);
         const int o = r * P16 + kg * 8;
-        split_store(&As[buf][0][o], &As[buf][1][o], &As[buf][2][o], &As[buf][3][o], ra[ps], sa);
+        split_store(&As[buf][0][o], &As[buf][1][o], &As[buf][2][o], &As[buf][3][o], ra[S % PF][ps], sa);
       }
     }
 #pragma unroll
@@ -106,7 +112,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
         int r, kg;
         LB::row_kg(c, r, kg);
         const int o = r * P16 + kg * 8;
-        split_store(&Bs[buf][0][o], &Bs[buf][1][o], &Bs[buf][2][o], &Bs[buf][3][o], rb[ps], sb);
+        split_store(&Bs[buf][0][o], &Bs[buf][1][o], &Bs[buf][2][o], &Bs[buf][3][o], rb[S % PF][ps], sb);
       }
     }
   };
@@ -121,23 +127,36 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
     }
 
   const int64_t nk = (p.K + BK - 1) / BK;
-  load_tiles(0);
-  store_tiles(0);
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  load_tiles(0, S0{});
+  if (PF == 1) {
+    store_tiles(0, S0{});
+  } else {
+    if (nk > 1) load_tiles(BK, S1{});
+    store_tiles(0, S0{});
+  }
   __syncthreads();
   const int lrow = lane & 31, g = lane >> 5;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+  // One k tile from LDS buffer S: prefetch tile kt+2 into register set S, run half
+  // of the MFMAs, convert + store tile kt+1 (register set S^1) into the other LDS
+  // buffer while they execute, run the other half.
+  auto step = [&](int64_t kt, const int cur, auto set) {
+    constexpr int S = decltype(set)::value;
+    using SN = std::integral_constant<int, S ^ 1>;
+    // the last two tiles re-load the final tile (in bounds) so the body has no branch
+    if (PF == 2) load_tiles((kt + 2 < nk ? kt + 2 : nk - 1) * BK, set);
+    if (PF == 1 && kt + 1 < nk) load_tiles((kt + 1) * BK, SN{});
     V8 arh[FM], arl[FM], aih[FM], ail[FM], naih[FM], nail[FM];
     V8 brh[FN], brl[FN], bih[FN], bil[FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
       const int o = (wm * WM + a * 32 + lrow) * P16 + g * 8;
-      arh[a] = *(const V8*)&As[buf][0][o];
-      arl[a] = *(const V8*)&As[buf][1][o];
-      aih[a] = *(const V8*)&As[buf][2][o];
-      ail[a] = *(const V8*)&As[buf][3][o];
+      arh[a] = *(const V8*)&As[cur][0][o];
+      arl[a] = *(const V8*)&As[cur][1][o];
+      aih[a] = *(const V8*)&As[cur][2][o];
+      ail[a] = *(const V8*)&As[cur][3][o];
       u4 t0 = *(u4*)&aih[a], t1 = *(u4*)&ail[a];
       t0 ^= 0x80008000u;  // flip the sign of both 16-bit halves
       t1 ^= 0x80008000u;
@@ -147,10 +166,10 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
       const int o = (wn * WN + b * 32 + lrow) * P16 + g * 8;
-      brh[b] = *(const V8*)&Bs[buf][0][o];
-      brl[b] = *(const V8*)&Bs[buf][1][o];
-      bih[b] = *(const V8*)&Bs[buf][2][o];
-      bil[b] = *(const V8*)&Bs[buf][3][o];
+      brh[b] = *(const V8*)&Bs[cur][0][o];
+      brl[b] = *(const V8*)&Bs[cur][1][o];
+      bih[b] = *(const V8*)&Bs[cur][2][o];
+      bil[b] = *(const V8*)&Bs[cur][3][o];
     }
 #pragma unroll
     for (int a = 0; a < FM; ++a)
@@ -173,6 +192,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
         cr[a][b] = H::mfma(arh[a], brl[b], cr[a][b]);
         ci[a][b] = H::mfma(arh[a], bil[b], ci[a][b]);
       }
+    if (PF == 2) store_tiles(cur ^ 1, SN{});  // on the last tile this fills the idle buffer
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -194,8 +214,27 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
         cr[a][b] = H::mfma(nail[a], bih[b], cr[a][b]);
         ci[a][b] = H::mfma(ail[a], brh[b], ci[a][b]);
       }
-    if (kt + 1 < nk) store_tiles(buf ^ 1);
+    if (PF == 1 && kt + 1 < nk) store_tiles(cur ^ 1, SN{});
+    if (PF == 2) {
+      // interleave: each MFMA followed by a few VALU (hi/lo conversion) and LDS ops
+#pragma unroll
+      for (int i = 0; i < 12 * FM * FN; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global read
+      }
+    }
     __syncthreads();
+  };
+  if (PF == 2) {
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      step(kt, 0, S0{});
+      if (kt + 1 < nk) step(kt + 1, 1, S1{});
+    }
+  } else {
+    for (int64_t kt = 0; kt < nk; ++kt) step(kt, (int)(kt & 1), S1{});
   }
 
   const float unscale = 1.f / (sa * sb);
@@ -211,8 +250,7 @@ static hipError_t launch_split(const GemmArgs& a, hipStream_t s) {
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
   if (nwg <= 0) return hipSuccess;
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool akc = a.bits ? a.a_kc != 0 : a.a_ks == 1;
-  const bool bkc = a.bits ? a.b_kc != 0 : a.b_ks == 1;
+  const bool akc = gemm_a_kc(a), bkc = gemm_b_kc(a);
   dim3 grid((unsigned)nwg), block(256);
   if (akc && bkc) hipLaunchKernelGGL((k_gemm_split<BM, BN, true, true, PREC>), grid, block, 0, s, a);
   else if (akc) hipLaunchKernelGGL((k_gemm_split<BM, BN, true, false, PREC>), grid, block, 0, s, a);

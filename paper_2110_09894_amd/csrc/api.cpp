@@ -19,6 +19,21 @@ using namespace qx;
 
 static thread_local std::string g_err;
 
+// Host BF16 rounding (nearest even), for leaves that are stored split.
+static uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_float(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 static qx_status fail(qx_status s, const std::string& m) {
   g_err = m;
   return s;
@@ -399,9 +414,24 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     const int64_t gb = std::max<int64_t>(256, (int64_t)p->pc.gathers.size() * p->pc.max_b * 8);
     if ((e = hipMalloc((void**)&p->d_gather, gb)) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(gather): ") + hipGetErrorString(e));
-    // leaves: complex128 -> complex64, round to nearest even
+    // leaves: complex128 -> complex64, round to nearest even; a leaf read by a split-BF16
+    // product holds its four BF16 planes (hi re, lo re, hi im, lo im) in the same bytes
     std::vector<float> h(2 * p->pc.leaf_pool_elems);
     for (size_t i = 0; i < h.size(); ++i) h[i] = (float)p->pc.leaf_data[i];
+    for (const Tensor& t : p->pc.tensors) {
+      if (!t.is_leaf || !t.split) continue;
+      const int64_t E = t.elems();
+      std::vector<uint16_t> planes(4 * E);
+      for (int64_t e = 0; e < E; ++e) {
+        const float re = h[2 * (t.leaf_off + e)], im = h[2 * (t.leaf_off + e) + 1];
+        const uint16_t rh = bf16_rne(re), ih = bf16_rne(im);
+        planes[e] = rh;
+        planes[E + e] = bf16_rne(re - bf16_float(rh));
+        planes[2 * E + e] = ih;
+        planes[3 * E + e] = bf16_rne(im - bf16_float(ih));
+      }
+      std::memcpy(&h[2 * t.leaf_off], planes.data(), planes.size() * sizeof(uint16_t));
+    }
     if ((e = hipMemcpyAsync(p->d_leaves, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMemcpyAsync(leaves): ") + hipGetErrorString(e));
@@ -643,9 +673,42 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   // 16-byte vector loads along k need even strides and an aligned base
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
-  gemm_epilogue_setup(g);
+  hipStream_t s = (hipStream_t)stream;
   const int tile = gemm_default_tile(M, N);
-  HIP_TRY(launch_gemm(g, precision, tile, (hipStream_t)stream));
+  if (precision != QX_SPLIT_BF16) {
+    gemm_args_setup(g);
+    HIP_TRY(launch_gemm(g, precision, tile, s));
+    return QX_OK;
+  }
+  // split BF16: the product reads pre-split operands, so split A and B into
+  // temporary planes [item][row][kp] (k zero-padded to a multiple of 16) first
+  const int64_t kp = (K + 15) / 16 * 16;
+  const int64_t pa = batch * M * kp, pb = batch * N * kp;
+  uint16_t *ta = nullptr, *tb = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&ta, pa * 8, s));
+  hipError_t e = hipMallocAsync((void**)&tb, pb * 8, s);
+  if (e != hipSuccess) {
+    hipFreeAsync(ta, s);
+    return fail(QX_ERR_HIP, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  }
+  SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, pa, (int32_t)batch};
+  SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, pb, (int32_t)batch};
+  e = launch_split_planes(sa, s);
+  if (e == hipSuccess) e = launch_split_planes(sb, s);
+  if (e == hipSuccess) {
+    g.a = (const QxCplx*)ta;
+    g.b = (const QxCplx*)tb;
+    g.K = kp;
+    g.a_ms = kp; g.a_ks = 1; g.b_ns = kp; g.b_ks = 1;
+    g.a_item = M * kp; g.b_item = N * kp;
+    g.a_ps = pa; g.b_ps = pb;
+    g.vec_a = g.vec_b = 1;
+    gemm_args_setup(g);
+    e = launch_gemm(g, precision, tile, s);
+  }
+  hipFreeAsync(ta, s);
+  hipFreeAsync(tb, s);
+  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("split-BF16 product: ") + hipGetErrorString(e));
   return QX_OK;
 }
 

@@ -1,8 +1,378 @@
-// Split-precision complex GEMM, BF16 hi+lo instantiations.
-#include "gemm_split.h"
+// Split-precision complex GEMM on BF16 matrix cores with pre-split operands.
+//
+// Both operands are stored split (four BF16 planes: re hi, re lo, im hi,
+// im lo; see split_format.h), so the k loop converts nothing:
+//   A B ~= Ah Bh + Ah Bl + Al Bh
+// per real product, accumulated in FP32 by v_mfma_f32_32x32x16_bf16, with the
+// complex product as four real ones (the sign of Im A Im B is applied by
+// flipping the sign bits of the Im A fragments).
+//
+// Staging.  A tile is ROWS rows x 16 k per plane; in LDS a plane is [row][16 k]
+// (32 bytes per row) and the two 16-byte halves of row r (k 0..7, 8..15) trade
+// places when bit 2 xor bit 3 of r is set, so the 8 or 16 rows one fragment
+// load touches at a time fall into distinct banks.  A k-contiguous operand is
+// copied global -> LDS directly (global_load_lds_dwordx4: each lane moves 16
+// bytes, and a wave's 64 lanes fill 1 KB = 32 rows of one plane), leaving no
+// staging registers; other operands go through registers.  Two LDS buffers
+// alternate: the copy of tile k+1 runs while tile k is multiplied.
+#include <type_traits>
+
+#include "gemm_common.h"
 
 namespace qx {
-hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
-  return launch_split_tile<QX_SPLIT_BF16>(a, tile, s);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int half_swap(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+
+__device__ __forceinline__ int64_t row_offset(const OperandView& v, int64_t r0, int r) {
+  return v.bits ? scatter_bits(r0, v.rs, v.nr) + scatter_bits(r, v.rs, v.nr) : (r0 + r) * v.ld_r;
 }
+__device__ __forceinline__ int64_t k_offset(const OperandView& v, int64_t k) {
+  return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
+}
+
+// Direct global -> LDS copy of a k-contiguous operand tile.  The 4 * ROWS / 32
+// one-KB pieces (plane, 32-row group) are dealt to the NW waves round-robin.
+template <int ROWS, int NW>
+struct DmaTile {
+  static constexpr int NRG = ROWS / 32;
+  static constexpr int NI = 4 * NRG / NW;  // pieces (copy instructions) per wave
+  static_assert(NI * NW == 4 * NRG, "pieces must divide evenly among the waves");
+  int64_t goff[NI];
+  __device__ inline void init(const OperandView& v, int64_t ps, int64_t r0, int wave, int lane) {
+    const int64_t k8 = k_offset(v, 8);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = wave + NW * j;
+      const int plane = i / NRG, rg = i % NRG;
+      const int row = rg * 32 + (lane >> 1);
+      const int kg = (lane & 1) ^ half_swap(row);
+      // rows past the end read row 0 of the tile: their results are never stored
+      const int r = r0 + row < v.rows ? row : 0;
+      goff[j] = plane * ps + row_offset(v, r0, r) + (kg ? k8 : 0);
+    }
+  }
+  __device__ inline void issue(const uint16_t* X, int64_t kb, char* region, int wave) const {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = wave + NW * j;
+      const int plane = i / NRG, rg = i % NRG;
+      // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
+#if defined(__HIP_DEVICE_COMPILE__)
+      __builtin_amdgcn_global_load_lds(X + goff[j] + kb, (lds_void*)(region + plane * ROWS * 32 + rg * 1024), 16,
+                                       0, 0);
+#endif
+    }
+  }
+};
+
+// Register-staged copy for an operand that is not k-contiguous: consecutive
+// lanes take consecutive rows, each lane gathers 8 k values of one row.
+template <int ROWS, int NT>
+struct RegTile {
+  static constexpr int CH = ROWS * 2;
+  static constexpr int P = (CH + NT - 1) / NT;
+  static constexpr int NI = 0;  // no direct copies
+  int64_t roff[P];
+  int lds[P];
+  u32x4 reg[P][4];
+  __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int c = tid + NT * s;
+      const int row = c % ROWS, kg = (c / ROWS) & 1;
+      const int r = r0 + row < v.rows ? row : 0;
+      roff[s] = row_offset(v, r0, r) + k_offset(v, kg * 8);
+      lds[s] = c < CH ? row * 32 + (kg ^ half_swap(row)) * 16 : -1;
+    }
+  }
+  __device__ inline void load(const OperandView& v, const uint16_t* X, int64_t ps, int64_t kb) {
+    int64_t jo[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) jo[j] = k_offset(v, j);
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint16_t* src = X + q * ps + roff[s] + kb;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          reg[s][q][j] = (uint32_t)src[jo[2 * j]] | ((uint32_t)src[jo[2 * j + 1]] << 16);
+      }
+  }
+  __device__ inline void store(char* region) const {
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+      if (lds[s] >= 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(u32x4*)(region + q * ROWS * 32 + lds[s]) = reg[s][q];
+      }
+  }
+};
+
+__device__ __forceinline__ v16f mfma(bf16x8 a, bf16x8 b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 neg(bf16x8 x) {
+  u32x4 t = __builtin_bit_cast(u32x4, x);
+  t ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, t);
+}
+
+// s_waitcnt for "at most n vector-memory operations outstanding" (expcnt and
+// lgkmcnt left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int I>
+using Int = std::integral_constant<int, I>;
+
+// Work-group barrier for the k loop.  __syncthreads() adds a release fence that
+// waits for every outstanding vector-memory operation, including the direct
+// copies still in flight into later stages; here the caller has already waited
+// for exactly the copies that must have landed (wait_vm), and LDS operations are
+// drained explicitly.  The empty asm statements keep the compiler from moving
+// memory accesses across the barrier.
+__device__ __forceinline__ void stage_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS reads and writes are done
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+}  // namespace
+
+// BM x BN work-group tile computed by WGM x WGN waves; NS LDS stages, so the
+// copy of k tile t + NS - 1 is in flight while tile t is multiplied.
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(64 * WGM * WGN, (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024) ? 2 : 1)
+void k_gemm_bf16s(GemmArgs p) {
+  constexpr int NW = WGM * WGN, NT = 64 * NW;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int ABYTES = 4 * BM * 32, BBYTES = 4 * BN * 32, BUF = ABYTES + BBYTES;
+  constexpr int STAGE = NW * 32 * 33 * 8;
+  constexpr int SMEM = NS * BUF > STAGE ? NS * BUF : STAGE;
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const TileCoord tc = tile_coord(p, BM, BN);
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(p.a) + tc.aoff;
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(p.b) + tc.boff;
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const OperandView va = view_a(p, nullptr), vb = view_b(p, nullptr);
+
+  typename std::conditional<A_KC, DmaTile<BM, NW>, RegTile<BM, NT>>::type sa;
+  typename std::conditional<B_KC, DmaTile<BN, NW>, RegTile<BN, NT>>::type sb;
+  if constexpr (A_KC) sa.init(va, p.a_ps, m0, wave, lane);
+  else sa.init(va, m0, tid);
+  if constexpr (B_KC) sb.init(vb, p.b_ps, n0, wave, lane);
+  else sb.init(vb, n0, tid);
+  constexpr int NI = decltype(sa)::NI + decltype(sb)::NI;  // direct copies per wave per k tile
+
+  const int64_t nk = p.K / 16;  // K is a multiple of 16 (checked by the launcher)
+  int64_t kf = 0, ka = 0, kb = 0;  // last k tile fetched and its operand offsets
+  // start the copy of k tile kf into LDS buffer bi (register-staged operands: the loads only)
+  auto fetch = [&](auto bsel) {
+    char* buf = smem + decltype(bsel)::value * BUF;
+    if constexpr (A_KC) sa.issue(A, ka, buf, wave);
+    else sa.load(va, A, p.a_ps, ka);
+    if constexpr (B_KC) sb.issue(B, kb, buf + ABYTES, wave);
+    else sb.load(vb, B, p.b_ps, kb);
+  };
+  auto commit = [&](auto bsel) {
+    char* buf = smem + decltype(bsel)::value * BUF;
+    if constexpr (!A_KC) sa.store(buf);
+    if constexpr (!B_KC) sb.store(buf + ABYTES);
+  };
+  auto advance = [&]() {
+    const int z = __builtin_ctzll(~(uint64_t)kf);
+    ka += p.a_kinc[z];
+    kb += p.b_kinc[z];
+    ++kf;
+  };
+
+  v16f cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      cr[a][b] = v16f{0};
+      ci[a][b] = v16f{0};
+    }
+
+  // prologue: tiles 0 .. NS - 2
+  fetch(Int<0>{});
+  commit(Int<0>{});
+  if constexpr (NS > 2) {
+    if (nk > 1) {
+      advance();
+      fetch(Int<1>{});
+      commit(Int<1>{});
+    }
+  }
+  if constexpr (NS > 3) {
+    if (nk > 2) {
+      advance();
+      fetch(Int<2>{});
+      commit(Int<2>{});
+    }
+  }
+  if (nk >= NS - 1) wait_vm<(NS - 2) * NI>();
+  else wait_vm<0>();
+  stage_barrier();
+
+  // fragment addresses: row = tile row of this lane, half = which 8 k of the 16
+  const int frow = lane & 31;
+  const int fhalf = ((lane >> 5) ^ half_swap(frow)) * 16;
+
+  auto step = [&](int64_t kt, auto bsel) {
+    constexpr int BI = decltype(bsel)::value;
+    using BF = Int<(BI + NS - 1) % NS>;
+    const bool more = kt + NS - 1 < nk;
+    if (more) {
+      advance();
+      fetch(BF{});
+    }
+    const char* bufA = smem + BI * BUF;
+    const char* bufB = bufA + ABYTES;
+    bf16x8 arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int o = (wm * WM + a * 32 + frow) * 32 + fhalf;
+      arh[a] = *(const bf16x8*)(bufA + 0 * BM * 32 + o);
+      arl[a] = *(const bf16x8*)(bufA + 1 * BM * 32 + o);
+      aih[a] = *(const bf16x8*)(bufA + 2 * BM * 32 + o);
+      ail[a] = *(const bf16x8*)(bufA + 3 * BM * 32 + o);
+    }
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int o = (wn * WN + b * 32 + frow) * 32 + fhalf;
+      brh[b] = *(const bf16x8*)(bufB + 0 * BN * 32 + o);
+      brl[b] = *(const bf16x8*)(bufB + 1 * BN * 32 + o);
+      bih[b] = *(const bf16x8*)(bufB + 2 * BN * 32 + o);
+      bil[b] = *(const bf16x8*)(bufB + 3 * BN * 32 + o);
+    }
+    // Im C += Im A Re B; Re C += Re A Re B; Im C += Re A Im B; Re C -= Im A Im B
+    // (hi hi, hi lo, lo hi each); consecutive products update different accumulators
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(aih[a], brh[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(arh[a], brh[b], cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(aih[a], brl[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(arh[a], brl[b], cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(ail[a], brh[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(arl[a], brh[b], cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      aih[a] = neg(aih[a]);
+      ail[a] = neg(ail[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(arh[a], bih[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(aih[a], bih[b], cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(arh[a], bil[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(aih[a], bil[b], cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) ci[a][b] = mfma(arl[a], bih[b], ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) cr[a][b] = mfma(ail[a], bih[b], cr[a][b]);
+    if (more) commit(BF{});
+    // this wave's copies of tile kt + 1 have landed once at most the later tiles'
+    // copies are outstanding; the barrier then publishes every wave's pieces
+    if (more) wait_vm<(NS - 2) * NI>();
+    else wait_vm<0>();
+    stage_barrier();
+  };
+  int64_t kt = 0;
+  for (; kt + NS <= nk; kt += NS) {
+    step(kt, Int<0>{});
+    step(kt + 1, Int<1>{});
+    if constexpr (NS > 2) step(kt + 2, Int<2>{});
+    if constexpr (NS > 3) step(kt + 3, Int<3>{});
+  }
+  if (kt < nk) step(kt, Int<0>{});
+  if constexpr (NS > 2)
+    if (kt + 1 < nk) step(kt + 1, Int<1>{});
+  if constexpr (NS > 3)
+    if (kt + 2 < nk) step(kt + 2, Int<2>{});
+
+  const OutMap om = out_map(p, m0, n0);
+  store_blocks<FM, FN, WM, WN, true>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, 1.f,
+                                     reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
+}
+
+template <int BM, int BN, int WGM, int WGN, int NS>
+static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
+  if (nwg <= 0) return hipSuccess;
+  if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+  const bool akc = gemm_a_kc(a), bkc = gemm_b_kc(a);
+  dim3 grid((unsigned)nwg), block(64 * WGM * WGN);
+  if (akc && bkc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, true, true>), grid, block, 0, s, a);
+  else if (akc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, true, false>), grid, block, 0, s, a);
+  else if (bkc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, false, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+#ifndef QX_BF16_NS128
+#define QX_BF16_NS128 2
+#endif
+
+hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
+  // operands must be stored split, and K a multiple of the 16-wide k tile
+  if (a.a_ps <= 0 || a.b_ps <= 0 || a.K % 16 != 0) return hipErrorInvalidValue;
+  switch (tile) {
+    case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2>(a, s);
+    case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3>(a, s);
+    case GEMM_TILE_64x128: return launch_bf16s<64, 128, 2, 2, 3>(a, s);
+    case GEMM_TILE_256x128: return launch_bf16s<256, 128, 4, 2, 3>(a, s);
+    case GEMM_TILE_128x256: return launch_bf16s<128, 256, 2, 4, 3>(a, s);
+    default: return launch_bf16s<128, 128, 2, 2, QX_BF16_NS128>(a, s);
+  }
+}
+
 }  // namespace qx

@@ -5,6 +5,7 @@
 #include "kargs.h"
 #include "kernels.h"
 #include "qxtn.h"
+#include "split_format.h"
 
 namespace qx {
 
@@ -180,10 +181,12 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
 // order of ascending output address, so the stores form contiguous runs for
 // any output index order.  Element e of a block (10 bits, ordered by output
 // stride) is split into a lane part (bits 0..5) and a store-step part (bits
-// 6..9); both offsets are sums of precomputed per-bit strides.
+// 6..9); both offsets are sums of precomputed per-bit strides.  coff: element
+// offset of the work-group's output (item and shared-slice offsets).  With
+// c_ps > 0 the output is written in split BF16 form.
 // stage: per-wave LDS area of 32 x 33 complex.
 template <int FM, int FN, int WM, int WN, bool UNROLL>
-__device__ inline void store_blocks(const GemmArgs& p, QxCplx* __restrict__ C, const OutMap& om, int64_t m0,
+__device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMap& om, int64_t m0,
                                     int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
                                     const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
   const int lrow = lane & 31, g = lane >> 5;
@@ -206,7 +209,7 @@ __device__ inline void store_blocks(const GemmArgs& p, QxCplx* __restrict__ C, c
         stage[(8 * (i / 4) + 4 * g + (i % 4)) * 33 + lrow] = QxCplx{cr[a][b][i] * scale, ci[a][b][i] * scale};
       __syncthreads();
       const int64_t lm0 = wm * WM + a * 32, ln0 = wn * WN + b * 32;
-      QxCplx* __restrict__ Cb = C + om.m(p, lm0) + om.n(p, ln0) + off_lane;
+      const int64_t eb = coff + om.m(p, lm0) + om.n(p, ln0) + off_lane;
       auto put = [&](int j) {
         int lm = lm_lane, ln = ln_lane;
         int64_t off = 0;
@@ -217,7 +220,11 @@ __device__ inline void store_blocks(const GemmArgs& p, QxCplx* __restrict__ C, c
             ln += p.ep_ln[6 + b2];
             off += p.ep_st[6 + b2];
           }
-        if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) Cb[off] = stage[lm * 33 + ln];
+        if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) {
+          const QxCplx v = stage[lm * 33 + ln];
+          if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, eb + off, v);
+          else p.c[eb + off] = v;
+        }
       };
       // a rolled loop keeps the FP32 kernel's registers low enough for two waves per SIMD
       if (UNROLL) {

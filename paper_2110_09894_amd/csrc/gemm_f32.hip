@@ -136,9 +136,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
     __syncthreads();
   }
 
-  QxCplx* __restrict__ C = p.c + tc.coff;
   const OutMap om = out_map(p, m0, n0);
-  store_blocks<FM, FN, WM, WN, false>(p, C, om, m0, n0, wm, wn, lane, cr, ci, 1.f, smem + wave * (32 * 33));
+  store_blocks<FM, FN, WM, WN, false>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, 1.f, smem + wave * (32 * 33));
 }
 
 template <int BM, int BN>

@@ -238,9 +238,8 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p) {
   }
 
   const float unscale = 1.f / (sa * sb);
-  QxCplx* __restrict__ C = p.c + tc.coff;
   const OutMap om = out_map(p, m0, n0);
-  store_blocks<FM, FN, WM, WN, true>(p, C, om, m0, n0, wm, wn, lane, cr, ci, unscale,
+  store_blocks<FM, FN, WM, WN, true>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, unscale,
                                reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
 }
 

@@ -14,6 +14,7 @@
 #include "kargs.h"
 #include "kernels.h"
 #include "qxtn.h"
+#include "split_format.h"
 
 namespace qx {
 
@@ -71,7 +72,8 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
       if (j < nkhi && ((kh >> j) & 1)) { ah += p.a_ks[8 + j]; bh += p.b_ks[8 + j]; }
     for (int kl = 0; kl < nlo; ++kl) acc = cmul_acc(acc, p.a[ah + ka[kl]], p.b[bh + kb[kl]]);
   }
-  p.c[(int64_t)item * p.c_item + o] = acc;
+  if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, (int64_t)item * p.c_item + o, acc);
+  else p.c[(int64_t)item * p.c_item + o] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -120,7 +122,20 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
   if (threadIdx.x == 0) {
     QxCplx r = {(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
                 (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
-    p.c[(int64_t)item * p.c_item + o] = r;
+    if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, (int64_t)item * p.c_item + o, r);
+    else p.c[(int64_t)item * p.c_item + o] = r;
+  }
+}
+
+// Complex64 matrices -> split BF16 planes [item][row][kp], k >= K zero-filled.
+__global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
+  const int64_t per = p.rows * p.kp;
+  const int64_t n = per * p.n_items;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t item = e / per, rk = e - item * per;
+    const int64_t r = rk / p.kp, k = rk - r * p.kp;
+    const QxCplx v = k < p.K ? p.in[item * p.in_item + r * p.ld_r + k * p.ld_k] : QxCplx{0.f, 0.f};
+    store_split(p.out, p.ps, e, v);
   }
 }
 
@@ -346,7 +361,7 @@ hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-void gemm_epilogue_setup(GemmArgs& g) {
+void gemm_args_setup(GemmArgs& g) {
   // the ten bits of a 32x32 block (m 0..4, n 0..4) in ascending order of output stride
   int64_t st[10];
   int id[10];
@@ -373,6 +388,23 @@ void gemm_epilogue_setup(GemmArgs& g) {
     g.ep_ln[i] = isn ? 1 << bit : 0;
     g.ep_st[i] = st[i] >= ((int64_t)1 << 62) ? 0 : st[i];
   }
+  // k-tile steps: tile t -> t + 1 sets bit z of t (its lowest zero bit) and clears the bits below
+  for (int z = 0; z < QX_GEMM_BITS; ++z) {
+    int64_t ia = 0, ib = 0;
+    if (!g.bits) {
+      ia = 16 * g.a_ks;
+      ib = 16 * g.b_ks;
+    } else if (4 + z < g.nk) {
+      ia = g.a_kst[4 + z];
+      ib = g.b_kst[4 + z];
+      for (int i = 0; i < z; ++i) {
+        ia -= g.a_kst[4 + i];
+        ib -= g.b_kst[4 + i];
+      }
+    }
+    g.a_kinc[z] = ia;
+    g.b_kinc[z] = ib;
+  }
 }
 
 hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s) {
@@ -392,6 +424,14 @@ hipError_t launch_block_advance(const BlockArgs& a, hipStream_t s) {
 }
 hipError_t launch_block_finish(const BlockArgs& a, double* amp, hipStream_t s) {
   hipLaunchKernelGGL(k_block_finish, dim3((unsigned)((a.n_items + 255) / 256)), dim3(256), 0, s, a, amp);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const SplitPlanesArgs& a, hipStream_t s) {
+  const int64_t n = a.rows * a.kp * a.n_items;
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n + 255) / 256;
+  hipLaunchKernelGGL(k_split_planes, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -97,6 +97,10 @@ struct Compiler {
 
   Compiler(PlanCore& p, std::string& e) : pc(p), err(e) {}
 
+  // elements of every item of tensor t: the plane stride of its split form
+  int64_t plane_stride(const Tensor& t) const { return t.elems() * (t.batched ? pc.max_b : 1); }
+  bool split_bf16() const { return pc.precision == QX_SPLIT_BF16; }
+
   bool is_fixed(int lab) const { return pc.kind[lab] == KIND_SLICE && pc.aux[lab] >= pc.js; }
   bool is_vary(int lab) const { return pc.kind[lab] == KIND_SLICE && pc.aux[lab] < pc.js; }
   bool is_out(int lab) const { return pc.kind[lab] == KIND_OUT; }
@@ -166,6 +170,7 @@ struct Compiler {
   // Copy tensor ti into layout [korder][F in ti's order][rest in ti's order] (fastest first).
   int emit_permute(int ti, const std::vector<int>& korder, const std::vector<int>& F) {
     const Tensor src = pc.tensors[ti];
+    if (src.split) err = "internal: permute of a split tensor";
     Tensor dst;
     dst.batched = src.batched;
     dst.phase = src.phase;
@@ -275,8 +280,12 @@ struct Compiler {
         if (pc.kind[lab] == KIND_REG) ++regw;
       pc.width = std::max(pc.width, regw);
     }
+    // split-BF16 plans store every matrix-product operand split; leaves are split at upload
+    if (split_bf16())
+      for (int t = 0; t < n; ++t)
+        if (nodes[t].parent >= 0 && nodes[nodes[t].parent].cls == CLS_GEMM) pc.tensors[nodes[t].tensor].split = true;
     for (int t = 0; t < n - 1; ++t)
-      if (!emit_node(n + t)) return false;
+      if (!emit_node(n + t) || !err.empty()) return false;
     pc.root = nodes[nn - 1].tensor;
     return true;
   }
@@ -411,6 +420,11 @@ struct Compiler {
     }
     g.a_kc = kca;
     g.b_kc = kcb;
+    if (split_bf16()) {
+      if (!XA.split || !XB.split) err = "internal: matrix-product operand not stored split";
+      g.a_ps = plane_stride(XA);
+      g.b_ps = plane_stride(XB);
+    }
     // 16-byte loads need 8-element alignment: arena tensors are 256-byte aligned and every
     // non-k stride of a k-contiguous operand is a multiple of 8
     g.vec_a = kca && (!XA.is_leaf || XA.leaf_off % 8 == 0);
@@ -424,7 +438,7 @@ struct Compiler {
       g.b_hs[i] = (int64_t)1 << pos_in(XB, horder[i]);
       g.c_hs[i] = (int64_t)1 << pos_in(out, horder[i]);
     }
-    gemm_epilogue_setup(g);
+    gemm_args_setup(g);
     op.kind = OP_GEMM;
     if (pc.precision == QX_SPLIT_FP16) {
       op.scale_slot = pc.n_scale_slots;
@@ -454,6 +468,7 @@ struct Compiler {
     Tensor out;
     out.batched = nd.batched;
     out.phase = nd.phase;
+    out.split = split_bf16() && nd.parent >= 0 && nodes[nd.parent].cls == CLS_GEMM;
     Op op;
     op.phase = nd.phase;
     const double items = nd.batched ? pc.max_b : 1;
@@ -555,9 +570,10 @@ struct Compiler {
     op.bytes = 8.0 * ((double)pc.tensors[op.in_a].elems() * ia + (double)pc.tensors[op.in_b].elems() * ib +
                       (double)O.elems() * items);
     const int64_t citem = O.batched ? O.elems() : 0;
-    if (op.kind == OP_SIMT) op.simt.c_item = citem;
-    if (op.kind == OP_GEMM) op.gemm.c_item = citem;
-    if (op.kind == OP_DOT) op.dot.c_item = citem;
+    const int64_t cps = O.split ? plane_stride(O) : 0;
+    if (op.kind == OP_SIMT) { op.simt.c_item = citem; op.simt.c_ps = cps; }
+    if (op.kind == OP_GEMM) { op.gemm.c_item = citem; op.gemm.c_ps = cps; }
+    if (op.kind == OP_DOT) { op.dot.c_item = citem; op.dot.c_ps = cps; }
     ops.push_back(op);
     return true;
   }

@@ -35,6 +35,7 @@ struct Tensor {
   int phase = PH_CONST;
   int64_t arena_off = -1;        // byte offset in the arena (non-leaf)
   int first_op = -1, last_op = -1;
+  bool split = false;            // stored as split BF16 planes (operand of a split-BF16 product)
   int64_t elems() const { return (int64_t)1 << lay.size(); }
 };
 

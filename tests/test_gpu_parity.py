@@ -16,6 +16,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_2110_09894_amd import qxtn  # noqa: E402
 from workloads import (circuit_to_network, random_grid_circuit, ghz_circuit, identity_circuit,  # noqa: E402
+                       dense_chain_network,
                        mirror_circuit, greedy_tree, tree_trimming, all_bitstrings, random_bitstrings,
                        configs)
 from tests._util import rms_err, gpu_amplitudes  # noqa: E402
@@ -243,3 +244,21 @@ def test_autotuned_plan_matches_oracle():
     got = gpu_amplitudes(plan, xs, (777, 778))
     want = np.array([oracle.contract_slice(net, tree, x, sl, 777) for x in xs])
     assert rms_err(got, want) < TOL_C64
+
+
+CHAIN_TREE = [(0, 1), (4, 2), (5, 3)]
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("order", [(True, True, True, True), (True, False, True, False), (False, False, False, False)])
+@pytest.mark.parametrize("sliced,js", [((), 0), ((5, 12), 2)])
+def test_dense_leaves_as_matrix_product_operands(precision, order, sliced, js):
+    """Dense random leaves read directly by matrix-core products: leaves whose
+    summed labels are (or are not) their fastest-varying ones, a product fed by a
+    small contraction, and a varying sliced index shared by both operands."""
+    net = dense_chain_network(5, order, seed=11)
+    xs = random_bitstrings(10, 16, 12)
+    plan = qxtn.Plan(net, CHAIN_TREE, list(sliced), max_bitstrings=64, precision=precision, slice_batch_log2=js)
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_sliced(net, CHAIN_TREE, xs, list(sliced))
+    assert rms_err(got, want) < (TOL_C64 if precision == "c64" else TOL_SPLIT)

@@ -79,3 +79,26 @@ def circuit_to_network(circ: Circuit) -> Network:
         for q, lab in zip(qs, new):
             cur[q] = lab
     return Network(tensors, indices, cur, n, name=circ.name)
+
+
+def dense_chain_network(group_bits: int = 5, slow_first=(True, True, True, True), seed: int = 0) -> Network:
+    """Four dense random leaves in a chain, A(q_lo, k) B(k, j) C(j, l) D(l, q_hi).
+
+    Each group holds ``group_bits`` labels; q_lo / q_hi are the output wires of
+    qubits 0..g-1 / g..2g-1.  ``slow_first[t]`` lists leaf t's first group
+    slowest (else its second group slowest), which decides whether the labels a
+    contraction sums over are the leaf's fastest-varying ones.  Entries are
+    complex normal, scaled so amplitudes are of order 2^-g.
+    """
+    g = int(group_bits)
+    groups = [list(range(i * g, (i + 1) * g)) for i in range(5)]
+    rng = np.random.default_rng(seed)
+    tensors, indices = [], []
+    for t in range(4):
+        first, second = groups[t], groups[t + 1]
+        ix = first + second if slow_first[t] else second + first
+        shape = (2,) * len(ix)
+        data = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0 * (1 << g))
+        tensors.append(data)
+        indices.append(tuple(ix))
+    return Network(tensors, indices, groups[0] + groups[4], 2 * g, name=f"chain{g}")

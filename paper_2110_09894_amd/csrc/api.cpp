@@ -14,6 +14,7 @@
 #include "kernels.h"
 #include "plan.h"
 #include "qxtn.h"
+#include "split_format.h"
 
 using namespace qx;
 
@@ -415,7 +416,8 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     if ((e = hipMalloc((void**)&p->d_gather, gb)) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMalloc(gather): ") + hipGetErrorString(e));
     // leaves: complex128 -> complex64, round to nearest even; a leaf read by a split-BF16
-    // product holds its four BF16 planes (hi re, lo re, hi im, lo im) in the same bytes
+    // product holds its split BF16 form (64-byte chunks of 8 elements: hi re, lo re,
+    // hi im, lo im) in the same bytes
     std::vector<float> h(2 * p->pc.leaf_pool_elems);
     for (size_t i = 0; i < h.size(); ++i) h[i] = (float)p->pc.leaf_data[i];
     for (const Tensor& t : p->pc.tensors) {
@@ -425,10 +427,10 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
       for (int64_t e = 0; e < E; ++e) {
         const float re = h[2 * (t.leaf_off + e)], im = h[2 * (t.leaf_off + e) + 1];
         const uint16_t rh = bf16_rne(re), ih = bf16_rne(im);
-        planes[e] = rh;
-        planes[E + e] = bf16_rne(re - bf16_float(rh));
-        planes[2 * E + e] = ih;
-        planes[3 * E + e] = bf16_rne(im - bf16_float(ih));
+        planes[split_off(e, 0)] = rh;
+        planes[split_off(e, 1)] = bf16_rne(re - bf16_float(rh));
+        planes[split_off(e, 2)] = ih;
+        planes[split_off(e, 3)] = bf16_rne(im - bf16_float(ih));
       }
       std::memcpy(&h[2 * t.leaf_off], planes.data(), planes.size() * sizeof(uint16_t));
     }
@@ -681,7 +683,7 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
     return QX_OK;
   }
   // split BF16: the product reads pre-split operands, so split A and B into
-  // temporary planes [item][row][kp] (k zero-padded to a multiple of 16) first
+  // temporaries [item][row][kp] (k zero-padded to a multiple of 16) first
   const int64_t kp = (K + 15) / 16 * 16;
   const int64_t pa = batch * M * kp, pb = batch * N * kp;
   uint16_t *ta = nullptr, *tb = nullptr;
@@ -691,8 +693,8 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
     hipFreeAsync(ta, s);
     return fail(QX_ERR_HIP, std::string("hipMallocAsync: ") + hipGetErrorString(e));
   }
-  SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, pa, (int32_t)batch};
-  SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, pb, (int32_t)batch};
+  SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, (int32_t)batch};
+  SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, (int32_t)batch};
   e = launch_split_planes(sa, s);
   if (e == hipSuccess) e = launch_split_planes(sb, s);
   if (e == hipSuccess) {
@@ -701,7 +703,7 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
     g.K = kp;
     g.a_ms = kp; g.a_ks = 1; g.b_ns = kp; g.b_ks = 1;
     g.a_item = M * kp; g.b_item = N * kp;
-    g.a_ps = pa; g.b_ps = pb;
+    g.a_split = g.b_split = 1;
     g.vec_a = g.vec_b = 1;
     gemm_args_setup(g);
     e = launch_gemm(g, precision, tile, s);

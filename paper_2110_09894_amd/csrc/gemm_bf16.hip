@@ -1,20 +1,22 @@
 // Split-precision complex GEMM on BF16 matrix cores with pre-split operands.
 //
-// Both operands are stored split (four BF16 planes: re hi, re lo, im hi,
-// im lo; see split_format.h), so the k loop converts nothing:
+// Both operands are stored split (split_format.h: 64-byte chunks of 8 elements
+// holding hi re, lo re, hi im, lo im), so the k loop converts nothing:
 //   A B ~= Ah Bh + Ah Bl + Al Bh
 // per real product, accumulated in FP32 by v_mfma_f32_32x32x16_bf16, with the
 // complex product as four real ones (the sign of Im A Im B is applied by
 // flipping the sign bits of the Im A fragments).
 //
-// Staging.  A tile is ROWS rows x 16 k per plane; in LDS a plane is [row][16 k]
-// (32 bytes per row) and the two 16-byte halves of row r (k 0..7, 8..15) trade
-// places when bit 2 xor bit 3 of r is set, so the 8 or 16 rows one fragment
-// load touches at a time fall into distinct banks.  A k-contiguous operand is
-// copied global -> LDS directly (global_load_lds_dwordx4: each lane moves 16
-// bytes, and a wave's 64 lanes fill 1 KB = 32 rows of one plane), leaving no
-// staging registers; other operands go through registers.  Two LDS buffers
-// alternate: the copy of tile k+1 runs while tile k is multiplied.
+// Staging.  A tile is ROWS rows x 16 k; in LDS a row is 128 bytes = eight
+// 16-byte slots, one per (k half g, plane q), and slot (g, q) of row r sits at
+// position (4 g + q) ^ f(r), f(r) = (r & 7) ^ ((r >> 3) & 1), so the 8 or 16
+// consecutive rows one fragment load reads at a time hit distinct banks.  A
+// k-contiguous operand row is one 128-byte line in memory (two 64-byte chunks
+// when k bit 3 is not the next stride), copied global -> LDS directly
+// (global_load_lds_dwordx4: each lane moves 16 bytes, and a wave's 64 lanes
+// fill 1 KB = 8 rows), leaving no staging registers; other operands go through
+// registers.  NS LDS stages rotate: the copy of tile k + NS - 1 runs while tile
+// k is multiplied.
 #include <type_traits>
 
 #include "gemm_common.h"
@@ -27,7 +29,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __forceinline__ int half_swap(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+// slot position of (k half g, plane q) in LDS row r
+__device__ __forceinline__ int slot_of(int r, int gq) { return gq ^ ((r & 7) ^ ((r >> 3) & 1)); }
 
 __device__ __forceinline__ int64_t row_offset(const OperandView& v, int64_t r0, int r) {
   return v.bits ? scatter_bits(r0, v.rs, v.nr) + scatter_bits(r, v.rs, v.nr) : (r0 + r) * v.ld_r;
@@ -36,36 +39,35 @@ __device__ __forceinline__ int64_t k_offset(const OperandView& v, int64_t k) {
   return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
 }
 
-// Direct global -> LDS copy of a k-contiguous operand tile.  The 4 * ROWS / 32
-// one-KB pieces (plane, 32-row group) are dealt to the NW waves round-robin.
+// Direct global -> LDS copy of a k-contiguous operand tile.  The ROWS / 8
+// one-KB pieces (8 rows each) are dealt to the NW waves round-robin; lane l of
+// a piece fills slot l & 7 of row l >> 3.  Element offsets of chunk starts are
+// multiples of 8 (k bits 0..2 are the three lowest strides), so a chunk's
+// plane q is the 16 bytes at BF16 offset 4 e0 + 8 q.
 template <int ROWS, int NW>
 struct DmaTile {
-  static constexpr int NRG = ROWS / 32;
-  static constexpr int NI = 4 * NRG / NW;  // pieces (copy instructions) per wave
-  static_assert(NI * NW == 4 * NRG, "pieces must divide evenly among the waves");
+  static constexpr int NP = ROWS / 8;
+  static constexpr int NI = NP / NW;  // pieces (copy instructions) per wave
+  static_assert(NI * NW == NP, "pieces must divide evenly among the waves");
   int64_t goff[NI];
-  __device__ inline void init(const OperandView& v, int64_t ps, int64_t r0, int wave, int lane) {
+  __device__ inline void init(const OperandView& v, int64_t r0, int wave, int lane) {
     const int64_t k8 = k_offset(v, 8);
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      const int i = wave + NW * j;
-      const int plane = i / NRG, rg = i % NRG;
-      const int row = rg * 32 + (lane >> 1);
-      const int kg = (lane & 1) ^ half_swap(row);
+      const int row = (wave + NW * j) * 8 + (lane >> 3);
+      const int gq = slot_of(row, lane & 7);  // slot_of is its own inverse
       // rows past the end read row 0 of the tile: their results are never stored
       const int r = r0 + row < v.rows ? row : 0;
-      goff[j] = plane * ps + row_offset(v, r0, r) + (kg ? k8 : 0);
+      goff[j] = 4 * (row_offset(v, r0, r) + ((gq >> 2) ? k8 : 0)) + 8 * (gq & 3);
     }
   }
+  // kb: element offset of the k tile origin (a multiple of 8)
   __device__ inline void issue(const uint16_t* X, int64_t kb, char* region, int wave) const {
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      const int i = wave + NW * j;
-      const int plane = i / NRG, rg = i % NRG;
       // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
 #if defined(__HIP_DEVICE_COMPILE__)
-      __builtin_amdgcn_global_load_lds(X + goff[j] + kb, (lds_void*)(region + plane * ROWS * 32 + rg * 1024), 16,
-                                       0, 0);
+      __builtin_amdgcn_global_load_lds(X + goff[j] + 4 * kb, (lds_void*)(region + (wave + NW * j) * 1024), 16, 0, 0);
 #endif
     }
   }
@@ -79,38 +81,40 @@ struct RegTile {
   static constexpr int P = (CH + NT - 1) / NT;
   static constexpr int NI = 0;  // no direct copies
   int64_t roff[P];
-  int lds[P];
+  int row[P], kg[P];
   u32x4 reg[P][4];
   __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const int c = tid + NT * s;
-      const int row = c % ROWS, kg = (c / ROWS) & 1;
-      const int r = r0 + row < v.rows ? row : 0;
-      roff[s] = row_offset(v, r0, r) + k_offset(v, kg * 8);
-      lds[s] = c < CH ? row * 32 + (kg ^ half_swap(row)) * 16 : -1;
+      row[s] = c < CH ? c % ROWS : -1;
+      kg[s] = (c / ROWS) & 1;
+      const int rr = c % ROWS;
+      const int r = r0 + rr < v.rows ? rr : 0;
+      roff[s] = row_offset(v, r0, r) + k_offset(v, kg[s] * 8);
     }
   }
-  __device__ inline void load(const OperandView& v, const uint16_t* X, int64_t ps, int64_t kb) {
+  __device__ inline void load(const OperandView& v, const uint16_t* X, int64_t kb) {
     int64_t jo[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) jo[j] = k_offset(v, j);
 #pragma unroll
     for (int s = 0; s < P; ++s)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint16_t* src = X + q * ps + roff[s] + kb;
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          reg[s][q][j] = (uint32_t)src[jo[2 * j]] | ((uint32_t)src[jo[2 * j + 1]] << 16);
-      }
+        for (int j = 0; j < 4; ++j) {
+          const int64_t e0 = roff[s] + kb + jo[2 * j], e1 = roff[s] + kb + jo[2 * j + 1];
+          reg[s][q][j] = (uint32_t)X[split_off(e0, q)] | ((uint32_t)X[split_off(e1, q)] << 16);
+        }
   }
   __device__ inline void store(char* region) const {
 #pragma unroll
     for (int s = 0; s < P; ++s)
-      if (lds[s] >= 0) {
+      if (row[s] >= 0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(u32x4*)(region + q * ROWS * 32 + lds[s]) = reg[s][q];
+        for (int q = 0; q < 4; ++q)
+          *(u32x4*)(region + row[s] * 128 + slot_of(row[s], kg[s] * 4 + q) * 16) = reg[s][q];
       }
   }
 };
@@ -158,7 +162,7 @@ void k_gemm_bf16s(GemmArgs p) {
   constexpr int NW = WGM * WGN, NT = 64 * NW;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int ABYTES = 4 * BM * 32, BBYTES = 4 * BN * 32, BUF = ABYTES + BBYTES;
+  constexpr int ABYTES = BM * 128, BBYTES = BN * 128, BUF = ABYTES + BBYTES;
   constexpr int STAGE = NW * 32 * 33 * 8;
   constexpr int SMEM = NS * BUF > STAGE ? NS * BUF : STAGE;
   __shared__ __attribute__((aligned(1024))) char smem[SMEM];
@@ -167,28 +171,30 @@ void k_gemm_bf16s(GemmArgs p) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
   const TileCoord tc = tile_coord(p, BM, BN);
-  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(p.a) + tc.aoff;
-  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(p.b) + tc.boff;
+  // split storage is addressed from the tensor base by element offset (split_off)
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(p.a);
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(p.b);
   const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
   const OperandView va = view_a(p, nullptr), vb = view_b(p, nullptr);
 
   typename std::conditional<A_KC, DmaTile<BM, NW>, RegTile<BM, NT>>::type sa;
   typename std::conditional<B_KC, DmaTile<BN, NW>, RegTile<BN, NT>>::type sb;
-  if constexpr (A_KC) sa.init(va, p.a_ps, m0, wave, lane);
+  if constexpr (A_KC) sa.init(va, m0, wave, lane);
   else sa.init(va, m0, tid);
-  if constexpr (B_KC) sb.init(vb, p.b_ps, n0, wave, lane);
+  if constexpr (B_KC) sb.init(vb, n0, wave, lane);
   else sb.init(vb, n0, tid);
   constexpr int NI = decltype(sa)::NI + decltype(sb)::NI;  // direct copies per wave per k tile
 
   const int64_t nk = p.K / 16;  // K is a multiple of 16 (checked by the launcher)
-  int64_t kf = 0, ka = 0, kb = 0;  // last k tile fetched and its operand offsets
+  // last k tile fetched and the element offsets of its origin in A and B
+  int64_t kf = 0, ka = tc.aoff, kb = tc.boff;
   // start the copy of k tile kf into LDS buffer bi (register-staged operands: the loads only)
   auto fetch = [&](auto bsel) {
     char* buf = smem + decltype(bsel)::value * BUF;
     if constexpr (A_KC) sa.issue(A, ka, buf, wave);
-    else sa.load(va, A, p.a_ps, ka);
+    else sa.load(va, A, ka);
     if constexpr (B_KC) sb.issue(B, kb, buf + ABYTES, wave);
-    else sb.load(vb, B, p.b_ps, kb);
+    else sb.load(vb, B, kb);
   };
   auto commit = [&](auto bsel) {
     char* buf = smem + decltype(bsel)::value * BUF;
@@ -232,9 +238,11 @@ void k_gemm_bf16s(GemmArgs p) {
   else wait_vm<0>();
   stage_barrier();
 
-  // fragment addresses: row = tile row of this lane, half = which 8 k of the 16
+  // fragment addresses: this lane's tile row (mod 32) and the four slots of its k half
   const int frow = lane & 31;
-  const int fhalf = ((lane >> 5) ^ half_swap(frow)) * 16;
+  int fo[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fo[q] = frow * 128 + slot_of(frow, (lane >> 5) * 4 + q) * 16;
 
   auto step = [&](int64_t kt, auto bsel) {
     constexpr int BI = decltype(bsel)::value;
@@ -249,19 +257,19 @@ void k_gemm_bf16s(GemmArgs p) {
     bf16x8 arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
-      const int o = (wm * WM + a * 32 + frow) * 32 + fhalf;
-      arh[a] = *(const bf16x8*)(bufA + 0 * BM * 32 + o);
-      arl[a] = *(const bf16x8*)(bufA + 1 * BM * 32 + o);
-      aih[a] = *(const bf16x8*)(bufA + 2 * BM * 32 + o);
-      ail[a] = *(const bf16x8*)(bufA + 3 * BM * 32 + o);
+      const char* r = bufA + (wm * WM + a * 32) * 128;
+      arh[a] = *(const bf16x8*)(r + fo[0]);
+      arl[a] = *(const bf16x8*)(r + fo[1]);
+      aih[a] = *(const bf16x8*)(r + fo[2]);
+      ail[a] = *(const bf16x8*)(r + fo[3]);
     }
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
-      const int o = (wn * WN + b * 32 + frow) * 32 + fhalf;
-      brh[b] = *(const bf16x8*)(bufB + 0 * BN * 32 + o);
-      brl[b] = *(const bf16x8*)(bufB + 1 * BN * 32 + o);
-      bih[b] = *(const bf16x8*)(bufB + 2 * BN * 32 + o);
-      bil[b] = *(const bf16x8*)(bufB + 3 * BN * 32 + o);
+      const char* r = bufB + (wn * WN + b * 32) * 128;
+      brh[b] = *(const bf16x8*)(r + fo[0]);
+      brl[b] = *(const bf16x8*)(r + fo[1]);
+      bih[b] = *(const bf16x8*)(r + fo[2]);
+      bil[b] = *(const bf16x8*)(r + fo[3]);
     }
     // Im C += Im A Re B; Re C += Re A Re B; Im C += Re A Im B; Re C -= Im A Im B
     // (hi hi, hi lo, lo hi each); consecutive products update different accumulators
@@ -364,7 +372,7 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
 
 hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
   // operands must be stored split, and K a multiple of the 16-wide k tile
-  if (a.a_ps <= 0 || a.b_ps <= 0 || a.K % 16 != 0) return hipErrorInvalidValue;
+  if (!a.a_split || !a.b_split || a.K % 16 != 0) return hipErrorInvalidValue;
   switch (tile) {
     case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2>(a, s);
     case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3>(a, s);

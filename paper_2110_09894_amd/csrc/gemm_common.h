@@ -183,7 +183,7 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
 // stride) is split into a lane part (bits 0..5) and a store-step part (bits
 // 6..9); both offsets are sums of precomputed per-bit strides.  coff: element
 // offset of the work-group's output (item and shared-slice offsets).  With
-// c_ps > 0 the output is written in split BF16 form.
+// c_split the output is written in split BF16 form.
 // stage: per-wave LDS area of 32 x 33 complex.
 template <int FM, int FN, int WM, int WN, bool UNROLL>
 __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMap& om, int64_t m0,
@@ -222,7 +222,7 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
           }
         if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) {
           const QxCplx v = stage[lm * 33 + ln];
-          if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, eb + off, v);
+          if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), eb + off, v);
           else p.c[eb + off] = v;
         }
       };

@@ -34,7 +34,7 @@ struct SimtArgs {
   const int64_t *a_gather, *b_gather;    // per-item offsets, or null
   int32_t n_out, n_k, n_items;
   int32_t pad_;
-  int64_t c_ps;                          // > 0: C is stored split (BF16 planes, plane stride)
+  int32_t c_split, pad2_;                // C is stored in split BF16 form
   int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];   // strides of output bit i (0 if absent)
   int64_t a_ks[QX_MAX_KBITS], b_ks[QX_MAX_KBITS]; // strides of contracted bit j
 };
@@ -48,8 +48,8 @@ struct SimtArgs {
 //   A(m, k) at sum_i bit_i(m) a_rs[i] + sum_j bit_j(k) a_kst[j], etc.
 // a_kc / b_kc: k bits 0..2 are unit-stride-contiguous (8 consecutive k values
 // are 8 consecutive elements), which enables 16-byte loads along k.
-// a_ps / b_ps / c_ps: plane stride (elements) of an operand stored split into
-// four BF16 planes (split-BF16 products), 0 for complex64 storage.
+// a_split / b_split / c_split: the operand is stored in split BF16 form
+// (split-BF16 products), else complex64.
 #define QX_GEMM_BITS 32
 struct GemmArgs {
   const QxCplx *a, *b;
@@ -63,7 +63,7 @@ struct GemmArgs {
   const float *a_scale, *b_scale;        // split FP16: power-of-two operand scales (null = 1)
   int32_t bits, nm, nn, nk;              // bit-scattered mode and log2 of M, N, K
   int32_t a_kc, b_kc;
-  int64_t a_ps, b_ps, c_ps;
+  int32_t a_split, b_split, c_split, pad_split_;
   // epilogue: the ten bits of a 32x32 block in ascending order of output stride,
   // each with its output stride and its contribution to the block-local m / n
   int64_t ep_st[10];
@@ -86,7 +86,7 @@ struct DotArgs {
   int64_t a_item, b_item, c_item;
   const int64_t *a_gather, *b_gather;
   int32_t n_out, n_items;
-  int64_t c_ps;                          // > 0: C is stored split (BF16 planes, plane stride)
+  int32_t c_split, pad2_;                // C is stored in split BF16 form
   int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];
 };
 
@@ -141,12 +141,12 @@ struct BlockArgs {
   int32_t js, n_items;
 };
 
-// Complex64 matrices -> split BF16 planes, k padded with zeros to kp:
-//   plane q of out[item][r][k'] from in[item * in_item + r * ld_r + k * ld_k]
+// Complex64 matrices -> split BF16 form, k padded with zeros to kp:
+//   out[item][r][k'] (split) = in[item * in_item + r * ld_r + k' * ld_k] for k' < K, else 0
 struct SplitPlanesArgs {
   const QxCplx *in;
   uint16_t *out;
-  int64_t rows, K, kp, ld_r, ld_k, in_item, ps;
+  int64_t rows, K, kp, ld_r, ld_k, in_item;
   int32_t n_items;
 };
 

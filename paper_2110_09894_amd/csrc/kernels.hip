@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
       if (j < nkhi && ((kh >> j) & 1)) { ah += p.a_ks[8 + j]; bh += p.b_ks[8 + j]; }
     for (int kl = 0; kl < nlo; ++kl) acc = cmul_acc(acc, p.a[ah + ka[kl]], p.b[bh + kb[kl]]);
   }
-  if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, (int64_t)item * p.c_item + o, acc);
+  if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc);
   else p.c[(int64_t)item * p.c_item + o] = acc;
 }
 
@@ -122,12 +122,12 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
   if (threadIdx.x == 0) {
     QxCplx r = {(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
                 (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
-    if (p.c_ps) store_split(reinterpret_cast<uint16_t*>(p.c), p.c_ps, (int64_t)item * p.c_item + o, r);
+    if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, r);
     else p.c[(int64_t)item * p.c_item + o] = r;
   }
 }
 
-// Complex64 matrices -> split BF16 planes [item][row][kp], k >= K zero-filled.
+// Complex64 matrices -> split BF16 form [item][row][kp], k >= K zero-filled.
 __global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
   const int64_t per = p.rows * p.kp;
   const int64_t n = per * p.n_items;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
     const int64_t item = e / per, rk = e - item * per;
     const int64_t r = rk / p.kp, k = rk - r * p.kp;
     const QxCplx v = k < p.K ? p.in[item * p.in_item + r * p.ld_r + k * p.ld_k] : QxCplx{0.f, 0.f};
-    store_split(p.out, p.ps, e, v);
+    store_split(p.out, e, v);
   }
 }
 

@@ -97,8 +97,6 @@ struct Compiler {
 
   Compiler(PlanCore& p, std::string& e) : pc(p), err(e) {}
 
-  // elements of every item of tensor t: the plane stride of its split form
-  int64_t plane_stride(const Tensor& t) const { return t.elems() * (t.batched ? pc.max_b : 1); }
   bool split_bf16() const { return pc.precision == QX_SPLIT_BF16; }
 
   bool is_fixed(int lab) const { return pc.kind[lab] == KIND_SLICE && pc.aux[lab] >= pc.js; }
@@ -422,8 +420,7 @@ struct Compiler {
     g.b_kc = kcb;
     if (split_bf16()) {
       if (!XA.split || !XB.split) err = "internal: matrix-product operand not stored split";
-      g.a_ps = plane_stride(XA);
-      g.b_ps = plane_stride(XB);
+      g.a_split = g.b_split = 1;
     }
     // 16-byte loads need 8-element alignment: arena tensors are 256-byte aligned and every
     // non-k stride of a k-contiguous operand is a multiple of 8
@@ -570,10 +567,10 @@ struct Compiler {
     op.bytes = 8.0 * ((double)pc.tensors[op.in_a].elems() * ia + (double)pc.tensors[op.in_b].elems() * ib +
                       (double)O.elems() * items);
     const int64_t citem = O.batched ? O.elems() : 0;
-    const int64_t cps = O.split ? plane_stride(O) : 0;
-    if (op.kind == OP_SIMT) { op.simt.c_item = citem; op.simt.c_ps = cps; }
-    if (op.kind == OP_GEMM) { op.gemm.c_item = citem; op.gemm.c_ps = cps; }
-    if (op.kind == OP_DOT) { op.dot.c_item = citem; op.dot.c_ps = cps; }
+    const int csplit = O.split ? 1 : 0;
+    if (op.kind == OP_SIMT) { op.simt.c_item = citem; op.simt.c_split = csplit; }
+    if (op.kind == OP_GEMM) { op.gemm.c_item = citem; op.gemm.c_split = csplit; }
+    if (op.kind == OP_DOT) { op.dot.c_item = citem; op.dot.c_split = csplit; }
     ops.push_back(op);
     return true;
   }

@@ -32,11 +32,16 @@ typedef __attribute__((address_space(3))) void lds_void;
 // slot position of (k half g, plane q) in LDS row r
 __device__ __forceinline__ int slot_of(int r, int gq) { return gq ^ ((r & 7) ^ ((r >> 3) & 1)); }
 
-__device__ __forceinline__ int64_t row_offset(const OperandView& v, int64_t r0, int r) {
-  return v.bits ? scatter_bits(r0, v.rs, v.nr) + scatter_bits(r, v.rs, v.nr) : (r0 + r) * v.ld_r;
+// offset of tile-local row r < 256 (its bits are disjoint from those of the tile origin)
+__device__ __forceinline__ int64_t row_offset(const OperandView& v, int r) {
+  return v.bits ? scatter_bits<8>(r, v.rs, v.nr) : (int64_t)r * v.ld_r;
 }
-__device__ __forceinline__ int64_t k_offset(const OperandView& v, int64_t k) {
-  return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
+__device__ __forceinline__ int64_t origin_offset(const OperandView& v, int64_t r0) {
+  return v.bits ? scatter_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
+}
+// k < 16
+__device__ __forceinline__ int64_t k_offset(const OperandView& v, int k) {
+  return v.bits ? scatter_bits<4>(k, v.ks, v.nk) : (int64_t)k * v.ld_k;
 }
 
 // Direct global -> LDS copy of a k-contiguous operand tile.  The ROWS / 8
@@ -44,31 +49,47 @@ __device__ __forceinline__ int64_t k_offset(const OperandView& v, int64_t k) {
 // a piece fills slot l & 7 of row l >> 3.  Element offsets of chunk starts are
 // multiples of 8 (k bits 0..2 are the three lowest strides), so a chunk's
 // plane q is the 16 bytes at BF16 offset 4 e0 + 8 q.
+#ifndef QX_BF16_VIA_REGS
+#define QX_BF16_VIA_REGS 0
+#endif
 template <int ROWS, int NW>
 struct DmaTile {
   static constexpr int NP = ROWS / 8;
-  static constexpr int NI = NP / NW;  // pieces (copy instructions) per wave
-  static_assert(NI * NW == NP, "pieces must divide evenly among the waves");
-  int64_t goff[NI];
+  static constexpr int NI = QX_BF16_VIA_REGS ? 0 : NP / NW;  // direct copies per wave
+  static constexpr int NJ = NP / NW;                          // pieces per wave
+  static_assert(NJ * NW == NP, "pieces must divide evenly among the waves");
+  int64_t goff[NJ];  // BF16 offset of this lane's 16 bytes, relative to the k tile origin
+  u32x4 reg[QX_BF16_VIA_REGS ? NJ : 1];
   __device__ inline void init(const OperandView& v, int64_t r0, int wave, int lane) {
-    const int64_t k8 = k_offset(v, 8);
+    const int64_t k8 = k_offset(v, 8), base = origin_offset(v, r0);
 #pragma unroll
-    for (int j = 0; j < NI; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       const int row = (wave + NW * j) * 8 + (lane >> 3);
       const int gq = slot_of(row, lane & 7);  // slot_of is its own inverse
       // rows past the end read row 0 of the tile: their results are never stored
       const int r = r0 + row < v.rows ? row : 0;
-      goff[j] = 4 * (row_offset(v, r0, r) + ((gq >> 2) ? k8 : 0)) + 8 * (gq & 3);
+      goff[j] = 4 * (base + row_offset(v, r) + ((gq >> 2) ? k8 : 0)) + 8 * (gq & 3);
     }
   }
   // kb: element offset of the k tile origin (a multiple of 8)
-  __device__ inline void issue(const uint16_t* X, int64_t kb, char* region, int wave) const {
+  __device__ inline void issue(const uint16_t* X, int64_t kb, char* region, int wave) {
 #pragma unroll
-    for (int j = 0; j < NI; ++j) {
-      // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
+    for (int j = 0; j < NJ; ++j) {
+      const uint16_t* src = X + 4 * kb + goff[j];
+      if (QX_BF16_VIA_REGS) {
+        reg[j] = *(const u32x4*)src;
+      } else {
+        // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
 #if defined(__HIP_DEVICE_COMPILE__)
-      __builtin_amdgcn_global_load_lds(X + goff[j] + 4 * kb, (lds_void*)(region + (wave + NW * j) * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src, (lds_void*)(region + (wave + NW * j) * 1024), 16, 0, 0);
 #endif
+      }
+    }
+  }
+  __device__ inline void store(char* region, int wave, int lane) const {
+    if (QX_BF16_VIA_REGS) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) *(u32x4*)(region + (wave + NW * j) * 1024 + lane * 16) = reg[j];
     }
   }
 };
@@ -84,6 +105,7 @@ struct RegTile {
   int row[P], kg[P];
   u32x4 reg[P][4];
   __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
+    const int64_t base = origin_offset(v, r0);
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const int c = tid + NT * s;
@@ -91,7 +113,7 @@ struct RegTile {
       kg[s] = (c / ROWS) & 1;
       const int rr = c % ROWS;
       const int r = r0 + rr < v.rows ? rr : 0;
-      roff[s] = row_offset(v, r0, r) + k_offset(v, kg[s] * 8);
+      roff[s] = base + row_offset(v, r) + k_offset(v, kg[s] * 8);
     }
   }
   __device__ inline void load(const OperandView& v, const uint16_t* X, int64_t kb) {
@@ -199,7 +221,9 @@ void k_gemm_bf16s(GemmArgs p) {
   auto commit = [&](auto bsel) {
     char* buf = smem + decltype(bsel)::value * BUF;
     if constexpr (!A_KC) sa.store(buf);
+    else sa.store(buf, wave, lane);
     if constexpr (!B_KC) sb.store(buf + ABYTES);
+    else sb.store(buf + ABYTES, wave, lane);
   };
   auto advance = [&]() {
     const int z = __builtin_ctzll(~(uint64_t)kf);

@@ -12,6 +12,7 @@ namespace qx {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ QxCplx cmul_acc(QxCplx acc, QxCplx a, QxCplx b) {
   acc.x = fmaf(a.x, b.x, acc.x);
@@ -29,10 +30,14 @@ __device__ __forceinline__ QxCplx cmul_acc(QxCplx acc, QxCplx a, QxCplx b) {
 // with coalesced 8-byte loads.  Row offsets are fixed per thread for the whole
 // kernel; the k offset of the tile origin is recomputed per k tile.
 // ---------------------------------------------------------------------------
+// Offset of index v under per-bit strides st[0..n): sum of st[i] over the set bits
+// i of v.  NB bounds the bits v can have; the loop is unrolled so the strides are
+// fetched together instead of one dependent load per bit.
+template <int NB = QX_GEMM_BITS>
 __device__ inline int64_t scatter_bits(int64_t v, const int64_t* st, int n) {
   int64_t off = 0;
-  for (int i = 0; i < n; ++i)
-    if ((v >> i) & 1) off += st[i];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) off += (i < n && ((v >> i) & 1)) ? st[i] : 0;
   return off;
 }
 
@@ -80,8 +85,8 @@ struct TileLoader {
       rloc[ps] = r;
       kgl[ps] = kg;
       rok[ps] = c < CH && r0 + r < v.rows;
-      roff[ps] = rbase + (v.bits ? scatter_bits(r, v.rs, v.nr) : (int64_t)r * v.ld_r);
-      kgoff[ps] = koff(v, kg * 8);
+      roff[ps] = rbase + (v.bits ? scatter_bits<8>(r, v.rs, v.nr) : (int64_t)r * v.ld_r);
+      kgoff[ps] = v.bits ? scatter_bits<4>(kg * 8, v.ks, v.nk) : kg * 8 * v.ld_k;
     }
   }
   // offset of k0 (a multiple of 16): bits 4 and up
@@ -91,7 +96,10 @@ struct TileLoader {
   // flight.  A k-contiguous operand is only used when the host has checked 16-byte
   // alignment and K % 8 == 0; every other operand takes the row-contiguous path.
   __device__ inline void load(const OperandView& v, int64_t k0, QxCplx (&reg)[P][8]) const {
-    const int64_t kb0 = kbase(v, k0);
+    load(v, k0, kbase(v, k0), reg);
+  }
+  // kb0: offset of k0, when the caller tracks it incrementally
+  __device__ inline void load(const OperandView& v, int64_t k0, int64_t kb0, QxCplx (&reg)[P][8]) const {
 #pragma unroll
     for (int ps = 0; ps < P; ++ps) {
       const int64_t kb = k0 + kgl[ps] * 8;
@@ -131,14 +139,14 @@ __device__ inline OperandView view_b(const GemmArgs& p, const QxCplx* X) {
   return v;
 }
 
-// Output offset of (m, n): m0 / n0 are tile origins, lm / ln offsets inside the tile.
+// Output offset of (m, n): m0 / n0 are tile origins, lm / ln (< 256) offsets inside the tile.
 struct OutMap {
   int64_t mbase, nbase;
   __device__ inline int64_t m(const GemmArgs& p, int64_t lm) const {
-    return p.bits ? mbase + scatter_bits(lm, p.c_mst, p.nm) : mbase + lm * p.c_ms;
+    return p.bits ? mbase + scatter_bits<8>(lm, p.c_mst, p.nm) : mbase + lm * p.c_ms;
   }
   __device__ inline int64_t n(const GemmArgs& p, int64_t ln) const {
-    return p.bits ? nbase + scatter_bits(ln, p.c_nst, p.nn) : nbase + ln;
+    return p.bits ? nbase + scatter_bits<8>(ln, p.c_nst, p.nn) : nbase + ln;
   }
 };
 __device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
@@ -155,14 +163,15 @@ struct TileCoord {
   int item;
   int64_t tm, tn, aoff, boff, coff;
 };
+// (the launchers keep the grid below 2^31 work-groups, so 32-bit division suffices)
 __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
-  const int64_t tiles_n = (p.N + BN - 1) / BN;
-  const int64_t tiles = ((p.M + BM - 1) / BM) * tiles_n;
-  const int64_t nwg = (int64_t)gridDim.x;
-  int64_t w = blockIdx.x;
-  const int64_t per = nwg / 8;
+  const uint32_t tiles_n = (uint32_t)((p.N + BN - 1) / BN);
+  const uint32_t tiles = (uint32_t)((p.M + BM - 1) / BM) * tiles_n;
+  const uint32_t nwg = gridDim.x;
+  uint32_t w = blockIdx.x;
+  const uint32_t per = nwg / 8;
   if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
-  const int64_t z = w / tiles, t = w % tiles;
+  const uint32_t z = w / tiles, t = w % tiles;
   TileCoord tc;
   tc.tm = t / tiles_n;
   tc.tn = t % tiles_n;
@@ -177,6 +186,17 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
   return tc;
 }
 
+// Orders this wave's LDS accesses before and after it (a wave's LDS operations
+// complete in issue order; the empty asm statements keep the compiler from
+// moving memory accesses across).  Unlike __syncthreads() it neither waits for
+// the other waves nor for outstanding global stores.
+__device__ __forceinline__ void wave_lds_fence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Epilogue: each 32x32 accumulator block goes through LDS and is stored in the
 // order of ascending output address, so the stores form contiguous runs for
 // any output index order.  Element e of a block (10 bits, ordered by output
@@ -184,12 +204,41 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
 // 6..9); both offsets are sums of precomputed per-bit strides.  coff: element
 // offset of the work-group's output (item and shared-slice offsets).  With
 // c_split the output is written in split BF16 form.
-// stage: per-wave LDS area of 32 x 33 complex.
+// stage: per-wave LDS area of 32 x 33 complex.  The caller has passed a
+// work-group barrier after the last LDS read of the k loop, so the stage areas
+// (which alias the operand buffers) are free; afterwards each wave only touches
+// its own area.
 template <int FM, int FN, int WM, int WN, bool UNROLL>
 __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMap& om, int64_t m0,
                                     int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
                                     const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
   const int lrow = lane & 31, g = lane >> 5;
+  // split output in chunks: this lane's two chunks (block-element bits 3..9 = lane + 64 s),
+  // their output offsets inside a block and the LDS stage index of each element
+  struct {
+    int64_t off[2];
+    int sidx[2][8];
+  } ck;
+  if (p.c_split && p.ep_chunk) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int ch = lane + 64 * s;
+      int lm = 0, ln = 0;
+      int64_t off = 0;
+#pragma unroll
+      for (int b2 = 0; b2 < 7; ++b2)
+        if ((ch >> b2) & 1) {
+          lm += p.ep_lm[3 + b2];
+          ln += p.ep_ln[3 + b2];
+          off += p.ep_st[3 + b2];
+        }
+      ck.off[s] = off;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        ck.sidx[s][i] = (lm + ((i & 1) ? p.ep_lm[0] : 0) + ((i & 2) ? p.ep_lm[1] : 0) + ((i & 4) ? p.ep_lm[2] : 0)) * 33 +
+                        ln + ((i & 1) ? p.ep_ln[0] : 0) + ((i & 2) ? p.ep_ln[1] : 0) + ((i & 4) ? p.ep_ln[2] : 0);
+    }
+  }
   int lm_lane = 0, ln_lane = 0;
   int64_t off_lane = 0;
 #pragma unroll
@@ -203,12 +252,47 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
-      __syncthreads();
+      wave_lds_fence();
 #pragma unroll
       for (int i = 0; i < 16; ++i)
         stage[(8 * (i / 4) + 4 * g + (i % 4)) * 33 + lrow] = QxCplx{cr[a][b][i] * scale, ci[a][b][i] * scale};
-      __syncthreads();
+      wave_lds_fence();
       const int64_t lm0 = wm * WM + a * 32, ln0 = wn * WN + b * 32;
+      if (p.c_split && p.ep_chunk) {
+        // split output whose 8-element chunks lie inside the block: a lane converts
+        // one chunk (block-element bits 0..2) and writes its four planes as 16-byte stores
+        uint16_t* __restrict__ C16 = reinterpret_cast<uint16_t*>(p.c);
+        const int64_t ebase = coff + om.m(p, lm0) + om.n(p, ln0);
+        const bool inside = m0 + lm0 + 32 <= p.M && n0 + ln0 + 32 <= p.N;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          uint32_t pl[4][4];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const QxCplx v = stage[ck.sidx[s][i]];
+            const uint16_t rh = bf16_bits(v.x), ih = bf16_bits(v.y);
+            const uint16_t h[4] = {rh, bf16_bits(v.x - bf16_value(rh)), ih, bf16_bits(v.y - bf16_value(ih))};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (i & 1) pl[q][i >> 1] |= (uint32_t)h[q] << 16;
+              else pl[q][i >> 1] = h[q];
+            }
+          }
+          const int64_t e0 = ebase + ck.off[s];  // a multiple of 8
+          if (inside) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *(v4u*)(C16 + split_chunk(e0) + 8 * q) = v4u{pl[q][0], pl[q][1], pl[q][2], pl[q][3]};
+          } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int lmi = ck.sidx[s][i] / 33, lni = ck.sidx[s][i] % 33;
+              if (m0 + lm0 + lmi < p.M && n0 + ln0 + lni < p.N) store_split(C16, e0 + i, stage[ck.sidx[s][i]]);
+            }
+          }
+        }
+        continue;
+      }
       const int64_t eb = coff + om.m(p, lm0) + om.n(p, ln0) + off_lane;
       auto put = [&](int j) {
         int lm = lm_lane, ln = ln_lane;

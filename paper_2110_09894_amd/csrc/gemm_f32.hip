@@ -40,9 +40,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   la.init(va, m0, tid);
   lb.init(vb, n0, tid);
   QxCplx ra[LA::P][8], rb[LB::P][8];
+  int64_t kao = 0, kbo = 0;  // offsets of the k tile last loaded
   auto load_tiles = [&](int64_t k0) {
-    la.load(va, k0, ra);
-    lb.load(vb, k0, rb);
+    la.load(va, k0, kao, ra);
+    lb.load(vb, k0, kbo, rb);
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
@@ -87,7 +88,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
   const int lrow = lane & 31, g = lane >> 5;
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+    if (kt + 1 < nk) {
+      const int z = __builtin_ctzll(~(uint64_t)kt);
+      kao += p.a_kinc[z];
+      kbo += p.b_kinc[z];
+      load_tiles((kt + 1) * BK);
+    }
     QxCplx fa[FM][8], fb[FN][8];
 #pragma unroll
     for (int a = 0; a < FM; ++a) {

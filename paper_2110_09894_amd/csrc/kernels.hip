@@ -388,6 +388,7 @@ void gemm_args_setup(GemmArgs& g) {
     g.ep_ln[i] = isn ? 1 << bit : 0;
     g.ep_st[i] = st[i] >= ((int64_t)1 << 62) ? 0 : st[i];
   }
+  g.ep_chunk = g.ep_st[0] == 1 && g.ep_st[1] == 2 && g.ep_st[2] == 4;
   // k-tile steps: tile t -> t + 1 sets bit z of t (its lowest zero bit) and clears the bits below
   for (int z = 0; z < QX_GEMM_BITS; ++z) {
     int64_t ia = 0, ib = 0;

@@ -20,7 +20,9 @@
 
 namespace qx {
 
-__host__ __device__ __forceinline__ int64_t split_off(int64_t e, int q) { return ((e >> 3) << 5) + (q << 3) + (e & 7); }
+// position of the 64-byte chunk holding element e (in BF16 units)
+__host__ __device__ __forceinline__ int64_t split_chunk(int64_t e) { return (e >> 3) << 5; }
+__host__ __device__ __forceinline__ int64_t split_off(int64_t e, int q) { return split_chunk(e) + (q << 3) + (e & 7); }
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 

@@ -32,6 +32,119 @@ METRIC = "amplitudes/s + complex TFLOP/s (% MFMA peak) vs plain c64; p50/p99 lat
 PEAKS = {"c64": 157.3e12, "split_bf16": 2516.6e12, "split_fp16": 2516.6e12}
 DTYPES = {"c64": "c64 (fp32 mfma)", "split_bf16": "bf16 hi+lo x3 (fp32 acc)", "split_fp16": "fp16 hi+lo x3 (fp32 acc)"}
 HBM_PEAK = 8.0e12
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "gemm_traffic_c2_30q_d12.md")
+KERNEL_NAMES = {"c64": "k_gemm_f32", "split_bf16": "k_gemm_bf16s", "split_fp16": "k_gemm_split"}
+COPY_BYTES = 1 << 30
+
+
+def sources_digest():
+    """Digest of the library sources: measured HBM traffic is only reported for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2110_09894_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary, or None if stale or absent."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("sources_digest") != sources_digest():
+        return None
+    k = blob.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy: the reference dispatch for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
+
+
+def summarize_traffic(run_dir):
+    """Builds the traffic summary from four rocprofv3 --pmc databases under ``run_dir``:
+    copy_fetch, copy_write (the calibration copy) and bench_fetch, bench_write (one timed c2 step of each
+    precision).  FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by bytes-moved / counter reading
+    of the copy, then averaged per launch over every launch of each matrix-product kernel."""
+    import glob
+    import sqlite3
+
+    def per_dispatch(tag, counter):
+        """[(kernel name, value)] for every dispatch inside a contract call (k_block_init .. k_block_finish)."""
+        dbs = glob.glob(os.path.join(run_dir, tag, "**", "*results.db"), recursive=True)
+        rows = []
+        for db in dbs:
+            con = sqlite3.connect(db)
+            rows += con.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                                "where counter_name = ? group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+        rows.sort()
+        out, inside = [], False
+        for _, name, val in rows:
+            if "k_block_init" in name:
+                inside = True
+            elif "k_block_finish" in name:
+                inside = False
+            elif inside or tag.startswith("copy"):
+                out.append((name, val))
+        return out
+
+    cal = {}
+    for counter, tag in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
+        d = per_dispatch(tag, counter)
+        name, val = max(d, key=lambda t: t[1])
+        cal[counter] = {"kernel": name[:80], "kib": val, "scale": COPY_BYTES / (val * 1024.0)}
+    kernels = {}
+    for short in KERNEL_NAMES.values():
+        f = [v for v in per_dispatch("bench_fetch", "FETCH_SIZE") if f"qx::{short}<" in v[0]]
+        w = [v for v in per_dispatch("bench_write", "WRITE_SIZE") if f"qx::{short}<" in v[0]]
+        if not f or not w:
+            continue
+        fb = sum(v for _, v in f) / len(f) * 1024.0 * cal["FETCH_SIZE"]["scale"]
+        wb = sum(v for _, v in w) / len(w) * 1024.0 * cal["WRITE_SIZE"]["scale"]
+        kernels[short] = {"launches": len(f), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                          "traffic_bytes_per_launch": fb + wb}
+    blob = {"sources_digest": sources_digest(), "calibration": cal, "kernels": kernels}
+    lines = ["# HBM traffic of the matrix-product kernels, c2 (30-qubit 5x6 grid, depth 12, 1024 slices, 256 bitstrings)",
+             "",
+             "Two counter passes over one timed `bench.py` step of each precision (every launch of each kernel inside",
+             "the contract call, autotuning trials excluded), each scaled by the same counter read on a plain 1 GiB",
+             "device copy (`bench.py --copy-calibration`):",
+             "",
+             "```",
+             "cd /tmp && export TMPDIR=/tmp",
+             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/traffic/copy_fetch -- python3 $R/bench.py --copy-calibration",
+             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/traffic/copy_write -- python3 $R/bench.py --copy-calibration",
+             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/traffic/bench_fetch -- python3 $R/bench.py --steps 1 --warmup 0 "
+             "--no-cpu-baseline --no-permute",
+             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/traffic/bench_write -- python3 $R/bench.py --steps 1 --warmup 0 "
+             "--no-cpu-baseline --no-permute",
+             "python3 $R/bench.py --summarize-traffic $R/gpurun_out/traffic",
+             "```",
+             "",
+             "| kernel | launches | fetch MB/launch | write MB/launch | traffic MB/launch |",
+             "|---|---|---|---|---|"]
+    for k, v in kernels.items():
+        lines.append(f"| {k} | {v['launches']} | {v['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{v['write_bytes_per_launch'] / 1e6:.1f} | {v['traffic_bytes_per_launch'] / 1e6:.1f} |")
+    lines += ["", "Calibration: " + ", ".join(f"{c}: {v['kib']:.0f} KiB read for {COPY_BYTES >> 20} MiB copied "
+                                           f"(scale {v['scale']:.3f})" for c, v in cal.items()),
+              "", "bench.py reports `roofline.traffic` from this table only while the library sources still hash to",
+              "`sources_digest`.", "", "```json", json.dumps(blob, indent=1), "```", ""]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines))
+    print(TRAFFIC_FILE)
 
 
 def cpu_baseline(w, tree, sliced, xs, seconds):
@@ -156,6 +269,68 @@ def c4_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def summarize_trace(db_path, log_path):
+    """Kernel-time summary of a ``rocprofv3 --kernel-trace --stats`` run of bench.py (3 timed steps, 1 warm-up)."""
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration from kernels order by start").fetchall()
+    top = {}
+    for name, dur in rows:
+        t = top.setdefault(name, [0, 0.0])
+        t[0] += 1
+        t[1] += dur * 1e-6
+    total = sum(v[1] for v in top.values())
+    # per kernel family, launches inside timed contract calls (the first call of each plan is the warm-up)
+    fam, calls, inside = {}, 0, False
+    for name, dur in rows:
+        if "k_block_init" in name:
+            calls += 1
+            inside = calls % 4 != 1
+        elif "k_block_finish" in name:
+            inside = False
+        elif inside:
+            for short in KERNEL_NAMES.values():
+                if f"qx::{short}<" in name:
+                    f = fam.setdefault(short, [0, 0.0])
+                    f[0] += 1
+                    f[1] += dur * 1e-6
+    line = None
+    for l in open(log_path):
+        if l.startswith("{"):
+            line = json.loads(l)
+    out = ["# Kernel time on the 30-qubit workload (5x6 grid, depth 12, 1024 slices, 256 bitstrings)", "",
+           "Command (repository root, one MI355X):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp",
+           "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace_c2 -o run -- python3 $R/bench.py --steps 3 "
+           "--warmup 1 --no-cpu-baseline --no-permute",
+           "python3 $R/bench.py --summarize-trace $R/gpurun_out/trace_c2/run_results.db $R/gpurun_out/trace_c2.log",
+           "```", "",
+           "The run makes a complex64 plan and a split-BF16 plan (both autotuned); each does 1 warm-up call (graph",
+           "replay) and 3 timed calls (launches bracketed by events).  Whole-run totals per kernel:", "",
+           "| kernel | calls | total ms | average ms | % of run |", "|---|---:|---:|---:|---:|"]
+    for name, (n, ms) in sorted(top.items(), key=lambda kv: -kv[1][1])[:20]:
+        out.append(f"| `{name[:90]}` | {n} | {ms:.0f} | {ms / n:.3f} | {100 * ms / total:.1f} |")
+    out += ["", "Matrix-product kernels (all tile shapes) inside the timed calls, against what bench.py measured",
+            "with HIP events in the same run:", ""]
+    for prec, short in KERNEL_NAMES.items():
+        if short not in fam:
+            continue
+        n, ms = fam[short]
+        r = None
+        if line is not None:
+            r = line.get("roofline") if prec == line["config"].get("precision") else line.get(prec, {}).get("roofline")
+        ev = f"bench.py: {r['avg_launch_ms']:.3f} ms per launch, {r['achieved']:.1f} TFLOP/s algorithmic = " \
+             f"{100 * r['frac']:.1f}% of {r['peak']:.1f} TFLOP/s (MFMA work {100 * r['mfma_util']:.1f}% of peak)" if r else ""
+        out.append(f"* `{short}` ({prec}): {n} launches, average {ms / n:.3f} ms.  {ev}")
+    if line is not None:
+        out += ["", "bench.py line of this run: c64 " + f"{line['value']:.1f} amplitudes/s"
+                + (f", split_bf16 {line['split_bf16']['value']:.1f} amplitudes/s" if "split_bf16" in line else "")]
+    path = os.path.join(PROFILES, "gemm_c2_30q_d12.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(path)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +348,19 @@ def main():
     ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
     ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
+    ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--summarize-traffic", metavar="DIR", help="write the HBM traffic summary from counter runs")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "LOG"), help="write the kernel-time summary")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(slices shard across GPUs by contiguous ranges, but no multi-GPU path is built)",
@@ -236,8 +423,9 @@ def main():
             g = timing["gemm"]
             ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
             r["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
-                             "unit": "TFLOP/s", "frac": ach / PEAKS[precision], "traffic": None,
-                             "kernel": "k_gemm_f32" if precision == "c64" else "k_gemm_split",
+                             "unit": "TFLOP/s", "frac": ach / PEAKS[precision],
+                             "traffic": measured_traffic(KERNEL_NAMES[precision]),
+                             "kernel": KERNEL_NAMES[precision],
                              "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
                              "launches_per_step": g["launches"] / args.steps,
                              "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}

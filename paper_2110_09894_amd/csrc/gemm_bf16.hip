@@ -207,7 +207,7 @@ void k_gemm_bf16s(GemmArgs p) {
   else sb.init(vb, n0, tid);
   constexpr int NI = decltype(sa)::NI + decltype(sb)::NI;  // direct copies per wave per k tile
 
-  const int64_t nk = p.K / 16;  // K is a multiple of 16 (checked by the launcher)
+  const int64_t nk = (p.K + 15) / 16;  // K is a multiple of 16, or 8 (checked by the launcher)
   // last k tile fetched and the element offsets of its origin in A and B
   int64_t kf = 0, ka = tc.aoff, kb = tc.boff;
   // start the copy of k tile kf into LDS buffer bi (register-staged operands: the loads only)
@@ -261,6 +261,17 @@ void k_gemm_bf16s(GemmArgs p) {
   if (nk >= NS - 1) wait_vm<(NS - 2) * NI>();
   else wait_vm<0>();
   stage_barrier();
+  if (p.K == 8) {
+    // one k tile whose upper half (k 8..15) does not exist: the copies filled those
+    // slots with the lower half again (k bit 3 has no stride), so zero them
+    for (int i = tid; i < 4 * (BM + BN); i += NT) {
+      const int row = i >> 2, q = i & 3;
+      char* base = row < BM ? smem + row * 128 : smem + ABYTES + (row - BM) * 128;
+      const int r = row < BM ? row : row - BM;
+      *(u32x4*)(base + slot_of(r, 4 + q) * 16) = u32x4{0, 0, 0, 0};
+    }
+    stage_barrier();
+  }
 
   // fragment addresses: this lane's tile row (mod 32) and the four slots of its k half
   const int frow = lane & 31;
@@ -395,8 +406,8 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
 #endif
 
 hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
-  // operands must be stored split, and K a multiple of the 16-wide k tile
-  if (!a.a_split || !a.b_split || a.K % 16 != 0) return hipErrorInvalidValue;
+  // operands must be stored split, and K a multiple of the 16-wide k tile (or 8: one half tile)
+  if (!a.a_split || !a.b_split || (a.K % 16 != 0 && a.K != 8)) return hipErrorInvalidValue;
   switch (tile) {
     case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2>(a, s);
     case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3>(a, s);

@@ -91,10 +91,11 @@ struct TileLoader {
   }
   // offset of k0 (a multiple of 16): bits 4 and up
   __device__ inline int64_t kbase(const OperandView& v, int64_t k0) const { return koff(v, k0); }
-  // Branch-free: invalid rows read row 0 of the tile origin (a valid address) and
-  // are zeroed with selects, so the compiler can keep several tiles of loads in
-  // flight.  A k-contiguous operand is only used when the host has checked 16-byte
-  // alignment and K % 8 == 0; every other operand takes the row-contiguous path.
+  // Branch-free: invalid rows, and k chunks past K, read row 0 of the tile origin
+  // (a valid address) and are zeroed with selects, so the compiler can keep several
+  // tiles of loads in flight.  A k-contiguous operand is only used when the host has
+  // checked 16-byte alignment and K % 8 == 0 (so a chunk is wholly inside or outside
+  // K); every other operand takes the row-contiguous path.
   __device__ inline void load(const OperandView& v, int64_t k0, QxCplx (&reg)[P][8]) const {
     load(v, k0, kbase(v, k0), reg);
   }
@@ -103,7 +104,7 @@ struct TileLoader {
 #pragma unroll
     for (int ps = 0; ps < P; ++ps) {
       const int64_t kb = k0 + kgl[ps] * 8;
-      const bool ok = rok[ps];
+      const bool ok = rok[ps] && (!KC || kb < v.K);
       const QxCplx* src = v.X + (ok ? roff[ps] : 0) + kb0 + kgoff[ps];
       if (KC) {
 #pragma unroll

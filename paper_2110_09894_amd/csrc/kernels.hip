@@ -21,6 +21,7 @@ namespace qx {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ QxCplx cmul_acc(QxCplx acc, QxCplx a, QxCplx b) {
   acc.x = fmaf(a.x, b.x, acc.x);
@@ -36,6 +37,7 @@ __device__ __forceinline__ QxCplx cmul_acc(QxCplx acc, QxCplx a, QxCplx b) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
   __shared__ int64_t ka[256], kb[256];
+  __shared__ __attribute__((aligned(16))) uint16_t sp[256 * 4];  // split output of the block's 256 elements
   const int nklo = p.n_k < 8 ? p.n_k : 8;
   const int nlo = 1 << nklo;
   for (int i = threadIdx.x; i < nlo; i += blockDim.x) {
@@ -47,9 +49,14 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
     kb[i] = ob;
   }
   __syncthreads();
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the block covers outputs [o0, o0 + blockDim): o0's bits (uniform) and the thread's bits are disjoint
+  const int tid = threadIdx.x;
+  const int64_t o0 = (int64_t)blockIdx.x * blockDim.x, o = o0 + tid;
+  const int64_t n = (int64_t)1 << p.n_out;
   const int item = blockIdx.y;
-  if (o >= ((int64_t)1 << p.n_out)) return;
+  // split output of full 256-element blocks goes through LDS and out as 16-byte stores
+  const bool chunked = p.c_split && blockDim.x == 256 && n >= 256;
+  if (o >= n) return;  // never taken by a chunked block
   int64_t ao = (int64_t)item * p.a_item + (p.a_gather ? p.a_gather[item] : 0);
   int64_t bo = (int64_t)item * p.b_item + (p.b_gather ? p.b_gather[item] : 0);
   if (p.block) {
@@ -62,18 +69,52 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
   }
 #pragma unroll
   for (int i = 0; i < QX_MAX_BITS; ++i)
-    if (i < p.n_out && ((o >> i) & 1)) { ao += p.a_os[i]; bo += p.b_os[i]; }
-  QxCplx acc = {0.f, 0.f};
-  const int nkhi = p.n_k - nklo;
-  for (int64_t kh = 0; kh < ((int64_t)1 << nkhi); ++kh) {
-    int64_t ah = ao, bh = bo;
+    if (i < p.n_out && ((o0 >> i) & 1)) { ao += p.a_os[i]; bo += p.b_os[i]; }
 #pragma unroll
-    for (int j = 0; j < QX_MAX_KBITS - 8; ++j)
-      if (j < nkhi && ((kh >> j) & 1)) { ah += p.a_ks[8 + j]; bh += p.b_ks[8 + j]; }
-    for (int kl = 0; kl < nlo; ++kl) acc = cmul_acc(acc, p.a[ah + ka[kl]], p.b[bh + kb[kl]]);
+  for (int i = 0; i < 8; ++i)
+    if (i < p.n_out && ((tid >> i) & 1)) { ao += p.a_os[i]; bo += p.b_os[i]; }
+  QxCplx acc = {0.f, 0.f};
+  if (p.n_k <= 3) {
+    // up to 8 terms: uniform offsets, every load issued before the first product
+    QxCplx xa[8], xb[8];
+#pragma unroll
+    for (int kl = 0; kl < 8; ++kl) {
+      if (kl < nlo) {
+        const int64_t oa = ((kl & 1) ? p.a_ks[0] : 0) + ((kl & 2) ? p.a_ks[1] : 0) + ((kl & 4) ? p.a_ks[2] : 0);
+        const int64_t ob = ((kl & 1) ? p.b_ks[0] : 0) + ((kl & 2) ? p.b_ks[1] : 0) + ((kl & 4) ? p.b_ks[2] : 0);
+        xa[kl] = p.a[ao + oa];
+        xb[kl] = p.b[bo + ob];
+      }
+    }
+#pragma unroll
+    for (int kl = 0; kl < 8; ++kl)
+      if (kl < nlo) acc = cmul_acc(acc, xa[kl], xb[kl]);
+  } else {
+    const int nkhi = p.n_k - nklo;
+    for (int64_t kh = 0; kh < ((int64_t)1 << nkhi); ++kh) {
+      int64_t ah = ao, bh = bo;
+#pragma unroll
+      for (int j = 0; j < QX_MAX_KBITS - 8; ++j)
+        if (j < nkhi && ((kh >> j) & 1)) { ah += p.a_ks[8 + j]; bh += p.b_ks[8 + j]; }
+      for (int kl = 0; kl < nlo; ++kl) acc = cmul_acc(acc, p.a[ah + ka[kl]], p.b[bh + kb[kl]]);
+    }
   }
-  if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc);
-  else p.c[(int64_t)item * p.c_item + o] = acc;
+  const int64_t e = (int64_t)item * p.c_item + o;
+  if (chunked) {
+    const uint16_t rh = bf16_bits(acc.x), ih = bf16_bits(acc.y);
+    sp[split_off(tid, 0)] = rh;
+    sp[split_off(tid, 1)] = bf16_bits(acc.x - bf16_value(rh));
+    sp[split_off(tid, 2)] = ih;
+    sp[split_off(tid, 3)] = bf16_bits(acc.y - bf16_value(ih));
+    __syncthreads();
+    // the block's elements e - tid .. e - tid + 255 (a multiple of 8 onwards) are 2 KB of split storage
+    if (tid < 128)
+      *(v4u*)(reinterpret_cast<uint16_t*>(p.c) + split_chunk(e - tid) + 8 * tid) = *(const v4u*)(sp + 8 * tid);
+  } else if (p.c_split) {
+    store_split(reinterpret_cast<uint16_t*>(p.c), e, acc);
+  } else {
+    p.c[e] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------

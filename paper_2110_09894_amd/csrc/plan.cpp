@@ -20,7 +20,7 @@
 //
 // Op classes.  A pairwise contraction with free dims M, N and contracted K
 // (all powers of two) runs as
-//   GEMM  complex matrix product on the matrix cores when M, N, K >= 16;
+//   GEMM  complex matrix product on the matrix cores when M, N >= 16, K >= 8;
 //         its operands must hold the free and contracted indices as two
 //         contiguous groups at the fast end, else an LDS-tiled permute copies
 //         them into that layout;
@@ -253,7 +253,7 @@ struct Compiler {
       nd.bits = set_or(set_or(nd.Fa, nd.Fb), nd.H);
       const int m = (int)nd.Fa.size(), nb = (int)nd.Fb.size(), k = (int)nd.K.size();
       const bool leaf_fixed = A.has_fixed || B.has_fixed;
-      if (!leaf_fixed && m >= 4 && nb >= 4 && k >= 4 && m + nb + k >= 15) nd.cls = CLS_GEMM;
+      if (!leaf_fixed && m >= 4 && nb >= 4 && k >= 3 && m + nb + k >= 15) nd.cls = CLS_GEMM;
       else if (!leaf_fixed && k >= 8) nd.cls = CLS_DOT;  // long sums: parallel reduction, never one thread
       else nd.cls = CLS_SIMT;
       if ((int)nd.bits.size() > QX_MAX_BITS) {
@@ -766,6 +766,9 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
         fprintf(stderr, " hs");
         for (int j = 0; j < o.gemm.nh; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_hs[j]);
       }
+      if (o.kind == OP_SIMT)
+        fprintf(stderr, " nout %d nk %d fixa %zu fixb %zu gath %d %d", o.simt.n_out, o.simt.n_k, o.fix_a.size(),
+                o.fix_b.size(), o.gather_a, o.gather_b);
       if (o.kind == OP_PERM) {
         fprintf(stderr, " in_pos");
         for (int j = 0; j < o.perm.rank; ++j) fprintf(stderr, " %d", o.perm.in_pos[j]);

@@ -69,7 +69,7 @@ def _gemm_case(M, N, K, akc, bkc, batch, seed, precision="c64"):
 
 
 @pytest.mark.parametrize("M,N,K", [(128, 128, 128), (256, 512, 64), (64, 64, 16), (37, 53, 19), (1, 1, 1),
-                                   (300, 129, 257), (32, 2048, 32), (512, 512, 512)])
+                                   (300, 129, 257), (32, 2048, 32), (512, 512, 512), (64, 96, 24), (80, 48, 8)])
 @pytest.mark.parametrize("akc,bkc", [(True, True), (True, False), (False, True), (False, False)])
 def test_cgemm_c64(M, N, K, akc, bkc):
     got, want, bound = _gemm_case(M, N, K, akc, bkc, 2, M * 7 + N * 3 + K)
@@ -86,7 +86,7 @@ SPLIT_REL = {"split_bf16": 6e-5, "split_fp16": 4e-6}
 
 @pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
 @pytest.mark.parametrize("M,N,K", [(128, 128, 128), (256, 512, 64), (64, 64, 16), (37, 53, 19), (300, 129, 257),
-                                   (512, 512, 512)])
+                                   (512, 512, 512), (64, 96, 24), (80, 48, 8)])
 @pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (True, False)])
 def test_cgemm_split(precision, M, N, K, akc, bkc):
     got, want, bound = _gemm_case(M, N, K, akc, bkc, 2, M * 5 + N * 11 + K, precision)

@@ -290,7 +290,7 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
       gemm_tile_dims(t, bm, bn);
       if (bm > std::max<int64_t>(64, g.M) || bn > std::max<int64_t>(64, g.N)) continue;
       float ms_min = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
+      for (int rep = 0; rep < 6; ++rep) {  // the first launch is a warm-up, the best of the others counts
         HIP_TRY(hipEventRecord(e0, s));
         HIP_TRY(launch_gemm(g, p->pc.precision, t, s));
         HIP_TRY(hipEventRecord(e1, s));

@@ -37,7 +37,7 @@ __device__ __forceinline__ int64_t row_offset(const OperandView& v, int r) {
   return v.bits ? scatter_bits<8>(r, v.rs, v.nr) : (int64_t)r * v.ld_r;
 }
 __device__ __forceinline__ int64_t origin_offset(const OperandView& v, int64_t r0) {
-  return v.bits ? scatter_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
+  return v.bits ? scatter_set_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
 }
 // k < 16
 __device__ __forceinline__ int64_t k_offset(const OperandView& v, int k) {

@@ -40,6 +40,16 @@ __device__ inline int64_t scatter_bits(int64_t v, const int64_t* st, int n) {
   for (int i = 0; i < NB; ++i) off += (i < n && ((v >> i) & 1)) ? st[i] : 0;
   return off;
 }
+// The same for a wave-uniform v with few set bits (tile origins): one step per set bit.
+__device__ inline int64_t scatter_set_bits(uint64_t v, const int64_t* st, int n) {
+  int64_t off = 0;
+  for (; v; v &= v - 1) {
+    const int i = __builtin_ctzll(v);
+    if (i >= n) break;
+    off += st[i];
+  }
+  return off;
+}
 
 // k-contiguous loading (8 consecutive k values with 16-byte loads) needs the
 // operand's k stride to be 1 for k bits 0..2, 16-byte alignment and K % 8 == 0.
@@ -76,7 +86,7 @@ struct TileLoader {
     return v.bits ? scatter_bits(k, v.ks, v.nk) : k * v.ld_k;
   }
   __device__ inline void init(const OperandView& v, int64_t r0, int tid) {
-    const int64_t rbase = v.bits ? scatter_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
+    const int64_t rbase = v.bits ? scatter_set_bits(r0, v.rs, v.nr) : r0 * v.ld_r;
 #pragma unroll
     for (int ps = 0; ps < P; ++ps) {
       const int c = tid + ps * 256;
@@ -152,8 +162,8 @@ struct OutMap {
 };
 __device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
   OutMap o;
-  o.mbase = p.bits ? scatter_bits(m0, p.c_mst, p.nm) : m0 * p.c_ms;
-  o.nbase = p.bits ? scatter_bits(n0, p.c_nst, p.nn) : n0;
+  o.mbase = p.bits ? scatter_set_bits(m0, p.c_mst, p.nm) : m0 * p.c_ms;
+  o.nbase = p.bits ? scatter_set_bits(n0, p.c_nst, p.nn) : n0;
   return o;
 }
 
@@ -181,9 +191,12 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
   tc.aoff = (int64_t)tc.item * p.a_item + (p.a_gather ? p.a_gather[tc.item] : 0);
   tc.boff = (int64_t)tc.item * p.b_item + (p.b_gather ? p.b_gather[tc.item] : 0);
   tc.coff = (int64_t)tc.item * p.c_item;
-#pragma unroll
-  for (int i = 0; i < QX_MAX_HBITS; ++i)
-    if (i < p.nh && ((h >> i) & 1)) { tc.aoff += p.a_hs[i]; tc.boff += p.b_hs[i]; tc.coff += p.c_hs[i]; }
+  for (uint32_t hb = h; hb; hb &= hb - 1) {
+    const int i = __builtin_ctz(hb);
+    tc.aoff += p.a_hs[i];
+    tc.boff += p.b_hs[i];
+    tc.coff += p.c_hs[i];
+  }
   return tc;
 }
 
@@ -269,15 +282,13 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
         for (int s = 0; s < 2; ++s) {
           uint32_t pl[4][4];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const QxCplx v = stage[ck.sidx[s][i]];
-            const uint16_t rh = bf16_bits(v.x), ih = bf16_bits(v.y);
-            const uint16_t h[4] = {rh, bf16_bits(v.x - bf16_value(rh)), ih, bf16_bits(v.y - bf16_value(ih))};
+          for (int d = 0; d < 4; ++d) {
+            uint32_t hi0, lo0, hi1, lo1, w[4];
+            split_pair(stage[ck.sidx[s][2 * d]], hi0, lo0);
+            split_pair(stage[ck.sidx[s][2 * d + 1]], hi1, lo1);
+            split_words(hi0, lo0, hi1, lo1, w);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (i & 1) pl[q][i >> 1] |= (uint32_t)h[q] << 16;
-              else pl[q][i >> 1] = h[q];
-            }
+            for (int q = 0; q < 4; ++q) pl[q][d] = w[q];
           }
           const int64_t e0 = ebase + ck.off[s];  // a multiple of 8
           if (inside) {

@@ -101,11 +101,12 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
   }
   const int64_t e = (int64_t)item * p.c_item + o;
   if (chunked) {
-    const uint16_t rh = bf16_bits(acc.x), ih = bf16_bits(acc.y);
-    sp[split_off(tid, 0)] = rh;
-    sp[split_off(tid, 1)] = bf16_bits(acc.x - bf16_value(rh));
-    sp[split_off(tid, 2)] = ih;
-    sp[split_off(tid, 3)] = bf16_bits(acc.y - bf16_value(ih));
+    uint32_t hi, lo;
+    split_pair(acc, hi, lo);
+    sp[split_off(tid, 0)] = (uint16_t)hi;
+    sp[split_off(tid, 1)] = (uint16_t)lo;
+    sp[split_off(tid, 2)] = (uint16_t)(hi >> 16);
+    sp[split_off(tid, 3)] = (uint16_t)(lo >> 16);
     __syncthreads();
     // the block's elements e - tid .. e - tid + 255 (a multiple of 8 onwards) are 2 KB of split storage
     if (tid < 128)

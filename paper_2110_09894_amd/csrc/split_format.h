@@ -28,14 +28,35 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) { return __builtin_bit_ca
 
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+typedef __bf16 qx_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float qx_f32x2 __attribute__((ext_vector_type(2)));
+
+// hi = [hi(re) | hi(im) << 16], lo = [lo(re) | lo(im) << 16] of one complex value
+__device__ __forceinline__ void split_pair(QxCplx v, uint32_t& hi, uint32_t& lo) {
+  const qx_f32x2 x = {v.x, v.y};
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, qx_bf16x2));
+  const qx_f32x2 h = {__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(x - h, qx_bf16x2));
+}
+
+// Packs the planes of two consecutive elements (pairs of split_pair) into plane words:
+// w[q] = plane q of element 2j in the low half, of element 2j + 1 in the high half.
+__device__ __forceinline__ void split_words(uint32_t hi0, uint32_t lo0, uint32_t hi1, uint32_t lo1, uint32_t (&w)[4]) {
+  w[0] = __builtin_amdgcn_perm(hi1, hi0, 0x05040100u);
+  w[1] = __builtin_amdgcn_perm(lo1, lo0, 0x05040100u);
+  w[2] = __builtin_amdgcn_perm(hi1, hi0, 0x07060302u);
+  w[3] = __builtin_amdgcn_perm(lo1, lo0, 0x07060302u);
+}
+
 // Writes element e of a split tensor whose storage starts at base.
 __device__ __forceinline__ void store_split(uint16_t* __restrict__ base, int64_t e, QxCplx v) {
-  const uint16_t rh = bf16_bits(v.x), ih = bf16_bits(v.y);
+  uint32_t hi, lo;
+  split_pair(v, hi, lo);
   uint16_t* __restrict__ c = base + split_off(e, 0);
-  c[0] = rh;
-  c[8] = bf16_bits(v.x - bf16_value(rh));
-  c[16] = ih;
-  c[24] = bf16_bits(v.y - bf16_value(ih));
+  c[0] = (uint16_t)hi;
+  c[8] = (uint16_t)lo;
+  c[16] = (uint16_t)(hi >> 16);
+  c[24] = (uint16_t)(lo >> 16);
 }
 
 }  // namespace qx

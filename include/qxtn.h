@@ -72,7 +72,10 @@ typedef struct {
 typedef struct {
   int32_t precision;           /* qx_precision */
   int32_t max_bitstrings;      /* largest B a qx_contract call may pass (>= 1) */
-  int32_t slice_batch_log2;    /* sliced indices 0..j-1 vary inside one device pass; -1 = auto */
+  int32_t slice_batch_log2;    /* sliced indices 0..j-1 vary inside one device pass; -1 = auto:
+                                  the cheapest estimated j (matrix work plus launches per block)
+                                  whose plan fits hbm_budget_bytes, or when that is 0, 96 GiB and
+                                  (unless dry_run) 80% of the device's free memory */
   int32_t dry_run;             /* non-zero: compile on the host only, touch no device */
   int64_t hbm_budget_bytes;    /* 0 = no limit */
   int32_t autotune;            /* non-zero: time every matrix-core tile shape that fits each

@@ -45,17 +45,19 @@ def _bucket(b: int, cap: int) -> int:
 
 
 class _Circuit:
-    def __init__(self, name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune):
+    def __init__(self, name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune,
+                 plan_budget):
         self.name = name
         self.network = network
         self.tree = tree
         self.sliced = list(sliced)
         self.precision = precision
         self.max_b = int(max_bitstrings)
-        self.js = slice_batch_log2
         self.autotune = autotune
+        # the slice batch is resolved once (within the per-plan budget) so every replica is the same plan
         dry = qxtn.Plan(network, tree, self.sliced, precision=precision, max_bitstrings=self.max_b,
-                        slice_batch_log2=slice_batch_log2, dry_run=True)
+                        slice_batch_log2=slice_batch_log2, dry_run=True, hbm_budget_bytes=plan_budget)
+        self.js = dry.info()["slice_batch_log2"]
         self.device_bytes = dry.info()["device_bytes"]
         self.n_slices = 1 << len(self.sliced)
         self.n_qubits = network.n_qubits
@@ -98,8 +100,11 @@ class _Request:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, max_replicas: int = 2, device: int = 0):
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, max_replicas: int = 2, device: int = 0,
+                 plan_budget_bytes: int | None = None):
         self.budget = int(hbm_budget_bytes)
+        # one plan's share when its slice batch is chosen automatically
+        self.plan_budget = int(plan_budget_bytes) if plan_budget_bytes else max(1 << 30, self.budget // 8)
         self.max_replicas = int(max_replicas)
         self.device = device
         self.circuits = {}
@@ -116,7 +121,8 @@ class Server:
     # ------------------------------------------------------------------ setup
     def register(self, name, network, tree, sliced=(), precision="c64", max_bitstrings=1024,
                  slice_batch_log2=-1, autotune=False):
-        circ = _Circuit(name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune)
+        circ = _Circuit(name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune,
+                        self.plan_budget)
         if circ.device_bytes > self.budget:
             raise AdmissionError(f"plan for {name} needs {circ.device_bytes} bytes, budget {self.budget}")
         with self.lock:

@@ -227,6 +227,38 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
                                     int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
                                     const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
   const int lrow = lane & 31, g = lane >> 5;
+  if (p.c_split && p.ep_reg) {
+    // A lane's accumulator group j (entries 8j .. 8j + 7) holds block rows 16j + 4g + {0..3, 8..11}
+    // of column lrow: with m bits 0, 1, 3 at output strides 1, 2, 4 that is one 8-element chunk,
+    // converted and written as four 16-byte stores without going through LDS.
+    uint16_t* __restrict__ C16 = reinterpret_cast<uint16_t*>(p.c);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int64_t lm0 = wm * WM + a * 32, ln0 = wn * WN + b * 32;
+        if (n0 + ln0 + lrow >= p.N) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (m0 + lm0 + 16 * j >= p.M) continue;
+          uint32_t pl[4][4];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            uint32_t hi0, lo0, hi1, lo1, w[4];
+            split_pair(QxCplx{cr[a][b][8 * j + 2 * d] * scale, ci[a][b][8 * j + 2 * d] * scale}, hi0, lo0);
+            split_pair(QxCplx{cr[a][b][8 * j + 2 * d + 1] * scale, ci[a][b][8 * j + 2 * d + 1] * scale}, hi1, lo1);
+            split_words(hi0, lo0, hi1, lo1, w);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pl[q][d] = w[q];
+          }
+          const int64_t e0 = coff + om.m(p, lm0 + 16 * j + 4 * g) + om.n(p, ln0 + lrow);  // a multiple of 8
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *(v4u*)(C16 + split_chunk(e0) + 8 * q) = v4u{pl[q][0], pl[q][1], pl[q][2], pl[q][3]};
+        }
+      }
+    return;
+  }
   // split output in chunks: this lane's two chunks (block-element bits 3..9 = lane + 64 s),
   // their output offsets inside a block and the LDS stage index of each element
   struct {

@@ -68,7 +68,8 @@ struct GemmArgs {
   // each with its output stride and its contribution to the block-local m / n
   int64_t ep_st[10];
   int32_t ep_lm[10], ep_ln[10];
-  int32_t ep_chunk, pad_ep_;             // the three lowest of those strides are 1, 2, 4
+  int32_t ep_chunk;                      // the three lowest of those strides are 1, 2, 4
+  int32_t ep_reg;                        // split output: m bits 0, 1, 3 have output strides 1, 2, 4
   int64_t a_hs[QX_MAX_HBITS], b_hs[QX_MAX_HBITS], c_hs[QX_MAX_HBITS];
   int64_t a_rs[QX_GEMM_BITS], a_kst[QX_GEMM_BITS];
   int64_t b_rs[QX_GEMM_BITS], b_kst[QX_GEMM_BITS];

@@ -352,6 +352,18 @@ struct Compiler {
       if (contains(nd.Fa, lab)) { a_is_n = true; break; }
       if (contains(nd.Fb, lab)) { a_is_n = false; break; }
     }
+    // A split output whose three lowest indices all come from one side can be written
+    // straight from the accumulators: that side becomes M, numbered so that m bits 0, 1, 3
+    // (the rows one lane holds in its accumulator groups) are those three indices.
+    bool ep_reg = false;
+    if (split_bf16() && out.split && out.lay.size() >= 3) {
+      const bool fa = contains(nd.Fa, out.lay[0]) && contains(nd.Fa, out.lay[1]) && contains(nd.Fa, out.lay[2]);
+      const bool fb = contains(nd.Fb, out.lay[0]) && contains(nd.Fb, out.lay[1]) && contains(nd.Fb, out.lay[2]);
+      if ((fa && nd.Fa.size() >= 4) || (fb && nd.Fb.size() >= 4)) {
+        ep_reg = true;
+        a_is_n = !fa;
+      }
+    }
     const int tA = a_is_n ? tb : ta, tB = a_is_n ? ta : tb;
     const std::vector<int>& FA = a_is_n ? nd.Fb : nd.Fa;
     const std::vector<int>& FB = a_is_n ? nd.Fa : nd.Fb;
@@ -366,7 +378,9 @@ struct Compiler {
       std::sort(v.begin(), v.end(), [&](int x, int y) { return pos_in(out, x) < pos_in(out, y); });
       return v;
     };
-    const std::vector<int> mlab = by_out(FA), nlab = by_out(FB);
+    std::vector<int> mlab = by_out(FA);
+    const std::vector<int> nlab = by_out(FB);
+    if (ep_reg) std::swap(mlab[2], mlab[3]);
     // k numbering: three unit-stride k bits first when an operand has them lowest
     auto low3 = [&](const Tensor& t) {
       return t.lay.size() >= 3 && contains(nd.K, t.lay[0]) && contains(nd.K, t.lay[1]) &&
@@ -436,6 +450,7 @@ struct Compiler {
       g.c_hs[i] = (int64_t)1 << pos_in(out, horder[i]);
     }
     gemm_args_setup(g);
+    g.ep_reg = ep_reg;
     op.kind = OP_GEMM;
     if (pc.precision == QX_SPLIT_FP16) {
       op.scale_slot = pc.n_scale_slots;

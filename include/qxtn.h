@@ -206,7 +206,12 @@ qx_status qx_permute_c64(const void *d_in, void *d_out, int32_t rank, const int3
  * Element (m, k) of A item z is at d_a + z*stride_a + m*a_ms + k*a_ks; one of
  * a_ms, a_ks must be 1.  B likewise with (k, n) strides b_ks, b_ns.  C item z
  * is dense row-major [M][N] at d_c + z*stride_c.  All strides in complex
- * elements.  precision: qx_precision.  M, N, K >= 1.
+ * elements.  precision: qx_precision.  M, N, K >= 1.  Asynchronous on stream.
+ * QX_SPLIT_BF16 first splits A and B into stream-ordered temporaries
+ * (hipMallocAsync, 8*batch*(M+N)*roundup(K,16) bytes, freed on the stream);
+ * the split-BF16 products of a plan read operands their producers stored
+ * split and allocate nothing.  Errors: QX_ERR_INVALID_ARG (NULL pointer,
+ * sizes, strides), QX_ERR_HIP (launch or allocation failure).
  */
 qx_status qx_cgemm(const void *d_a, const void *d_b, void *d_c, int64_t M, int64_t N, int64_t K,
                    int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a,

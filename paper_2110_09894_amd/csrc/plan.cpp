@@ -780,6 +780,10 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
                                              (long long)o.gemm.ep_st[j]);
         fprintf(stderr, " hs");
         for (int j = 0; j < o.gemm.nh; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_hs[j]);
+        fprintf(stderr, " a_rs");
+        for (int j = 0; j < o.gemm.nm; ++j) fprintf(stderr, " %lld", (long long)o.gemm.a_rs[j]);
+        fprintf(stderr, " b_rs");
+        for (int j = 0; j < o.gemm.nn; ++j) fprintf(stderr, " %lld", (long long)o.gemm.b_rs[j]);
       }
       if (o.kind == OP_SIMT)
         fprintf(stderr, " nout %d nk %d fixa %zu fixb %zu gath %d %d", o.simt.n_out, o.simt.n_k, o.fix_a.size(),

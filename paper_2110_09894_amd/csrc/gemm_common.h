@@ -169,23 +169,33 @@ __device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
 
 // Work-group -> (batch item, hyper index, tile) with an XCD-aware order:
 // hardware deals work-groups round-robin over the 8 XCDs, so each XCD gets a
-// contiguous run of logical tiles and neighbours share its L2.
+// contiguous run of logical tiles and neighbours share its L2.  Inside one
+// product the tiles run in groups of QX_TILE_GROUP tile rows, m fastest, so the
+// work-groups resident on one XCD at a time cover a square-ish patch of C and
+// read few A and B panels, each shared by several of them through the L2.
+#ifndef QX_TILE_GROUP
+#define QX_TILE_GROUP 8
+#endif
 struct TileCoord {
   int item;
   int64_t tm, tn, aoff, boff, coff;
 };
 // (the launchers keep the grid below 2^31 work-groups, so 32-bit division suffices)
 __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
+  const uint32_t tiles_m = (uint32_t)((p.M + BM - 1) / BM);
   const uint32_t tiles_n = (uint32_t)((p.N + BN - 1) / BN);
-  const uint32_t tiles = (uint32_t)((p.M + BM - 1) / BM) * tiles_n;
+  const uint32_t tiles = tiles_m * tiles_n;
   const uint32_t nwg = gridDim.x;
   uint32_t w = blockIdx.x;
   const uint32_t per = nwg / 8;
   if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
   const uint32_t z = w / tiles, t = w % tiles;
+  const uint32_t group = (uint32_t)QX_TILE_GROUP * tiles_n;
+  const uint32_t g = t / group, first = g * (uint32_t)QX_TILE_GROUP, r = t - g * group;
+  const uint32_t gsz = tiles_m - first < (uint32_t)QX_TILE_GROUP ? tiles_m - first : (uint32_t)QX_TILE_GROUP;
   TileCoord tc;
-  tc.tm = t / tiles_n;
-  tc.tn = t % tiles_n;
+  tc.tm = first + r % gsz;
+  tc.tn = r / gsz;
   tc.item = (int)(z >> p.nh);
   const int64_t h = z & ((1LL << p.nh) - 1);
   tc.aoff = (int64_t)tc.item * p.a_item + (p.a_gather ? p.a_gather[tc.item] : 0);

@@ -176,8 +176,9 @@ __device__ __forceinline__ void stage_barrier() {
 
 }  // namespace
 
-// BM x BN work-group tile computed by WGM x WGN waves; NS LDS stages, so the
-// copy of k tile t + NS - 1 is in flight while tile t is multiplied.
+// BM x BN work-group tile computed by WGM x WGN waves; NS LDS stages.  Each
+// wave takes its fragments of k tile t into registers before tile t is
+// multiplied, so the copies of tiles t + 1 .. t + NS are in flight meanwhile.
 template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(64 * WGM * WGN, (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024) ? 2 : 1)
 void k_gemm_bf16s(GemmArgs p) {
@@ -241,24 +242,29 @@ void k_gemm_bf16s(GemmArgs p) {
       ci[a][b] = v16f{0};
     }
 
-  // prologue: tiles 0 .. NS - 2
+  // prologue: tiles 0 .. NS - 1, one per LDS buffer; then wait for tile 0
   fetch(Int<0>{});
   commit(Int<0>{});
-  if constexpr (NS > 2) {
-    if (nk > 1) {
-      advance();
-      fetch(Int<1>{});
-      commit(Int<1>{});
-    }
+  if (nk > 1) {
+    advance();
+    fetch(Int<1>{});
+    commit(Int<1>{});
   }
-  if constexpr (NS > 3) {
+  if constexpr (NS > 2) {
     if (nk > 2) {
       advance();
       fetch(Int<2>{});
       commit(Int<2>{});
     }
   }
-  if (nk >= NS - 1) wait_vm<(NS - 2) * NI>();
+  if constexpr (NS > 3) {
+    if (nk > 3) {
+      advance();
+      fetch(Int<3>{});
+      commit(Int<3>{});
+    }
+  }
+  if (nk >= NS) wait_vm<(NS - 1) * NI>();
   else wait_vm<0>();
   stage_barrier();
   if (p.K == 8) {
@@ -279,14 +285,12 @@ void k_gemm_bf16s(GemmArgs p) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) fo[q] = frow * 128 + slot_of(frow, (lane >> 5) * 4 + q) * 16;
 
+  // One k tile: every wave reads all its fragments of tile kt (buffer BI), a barrier
+  // frees the buffer, and the copy of tile kt + NS into it starts before the products
+  // run, so a copy has NS steps to land instead of NS - 1.
   auto step = [&](int64_t kt, auto bsel) {
     constexpr int BI = decltype(bsel)::value;
-    using BF = Int<(BI + NS - 1) % NS>;
-    const bool more = kt + NS - 1 < nk;
-    if (more) {
-      advance();
-      fetch(BF{});
-    }
+    const bool more = kt + NS < nk;
     const char* bufA = smem + BI * BUF;
     const char* bufB = bufA + ABYTES;
     bf16x8 arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
@@ -305,6 +309,11 @@ void k_gemm_bf16s(GemmArgs p) {
       brl[b] = *(const bf16x8*)(r + fo[1]);
       bih[b] = *(const bf16x8*)(r + fo[2]);
       bil[b] = *(const bf16x8*)(r + fo[3]);
+    }
+    stage_barrier();
+    if (more) {
+      advance();
+      fetch(bsel);
     }
     // Im C += Im A Re B; Re C += Re A Re B; Im C += Re A Im B; Re C -= Im A Im B
     // (hi hi, hi lo, lo hi each); consecutive products update different accumulators
@@ -361,12 +370,14 @@ void k_gemm_bf16s(GemmArgs p) {
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b) cr[a][b] = mfma(ail[a], bih[b], cr[a][b]);
-    if (more) commit(BF{});
+    if (more) commit(bsel);
     // this wave's copies of tile kt + 1 have landed once at most the later tiles'
     // copies are outstanding; the barrier then publishes every wave's pieces
-    if (more) wait_vm<(NS - 2) * NI>();
-    else wait_vm<0>();
-    stage_barrier();
+    if (kt + 1 < nk) {
+      if (more) wait_vm<(NS - 1) * NI>();
+      else wait_vm<0>();
+      stage_barrier();
+    }
   };
   int64_t kt = 0;
   for (; kt + NS <= nk; kt += NS) {

@@ -326,10 +326,14 @@ struct Compiler {
         }
       }
       if (!matched || Q.cls == CLS_GEMM) {
+        std::vector<int> kord;
         for (int lab : big.lay)
-          if (contains(kq, lab)) push(lab);
+          if (contains(kq, lab)) kord.push_back(lab);
         for (int lab : small.lay)
-          if (contains(kq, lab)) push(lab);
+          if (contains(kq, lab) && std::find(kord.begin(), kord.end(), lab) == kord.end()) kord.push_back(lab);
+        if (!matched && Q.cls == CLS_GEMM && split_bf16())
+          for (int lab : register_epilogue_lead(p, sib, kord)) push(lab);
+        for (int lab : kord) push(lab);
       }
       for (int lab : big.lay)
         if (contains(fq, lab)) push(lab);
@@ -339,6 +343,44 @@ struct Compiler {
     for (int lab : big.lay) push(lab);
     for (int lab : small.lay) push(lab);
     return ff;
+  }
+
+  // Node p and its sibling sib are the two operands of a split matrix product
+  // and p is laid out first; the sibling will copy p's three lowest indices
+  // (contracted ones, so both operands are read k-contiguously).  A split
+  // matrix product writes its result straight from the accumulators when its
+  // three lowest output indices lie on one operand side holding at least four
+  // free indices, so pick, from the contracted indices in the order kord, three
+  // that allow this for both producing products if possible, else for the one
+  // with the larger result.  Empty when neither can have it.
+  std::vector<int> register_epilogue_lead(int p, int sib, const std::vector<int>& kord) {
+    const Node& P = nodes[p];
+    const Node& S = nodes[sib];
+    auto side = [](const Node& x, int lab) { return contains(x.Fa, lab) ? 1 : contains(x.Fb, lab) ? 2 : 0; };
+    auto fits = [](const Node& x, int s) {
+      return (s == 1 && x.Fa.size() >= 4) || (s == 2 && x.Fb.size() >= 4);
+    };
+    auto weight = [&](const Node& x) {
+      return x.cls == CLS_GEMM ? std::ldexp(1.0, (int)x.bits.size()) * (x.batched ? pc.max_b : 1) : 0.0;
+    };
+    const double wp = weight(P), ws = weight(S);
+    std::vector<int> best;
+    double best_w = 0.0;
+    // sp / ss: required side in P / S, 0 = no requirement
+    for (int sp = 0; sp <= 2; ++sp)
+      for (int ss = 0; ss <= 2; ++ss) {
+        if ((sp && (wp == 0.0 || !fits(P, sp))) || (ss && (ws == 0.0 || !fits(S, ss)))) continue;
+        const double w = (sp ? wp : 0.0) + (ss ? ws : 0.0);
+        if (w <= best_w) continue;
+        std::vector<int> c;
+        for (int lab : kord)
+          if ((!sp || side(P, lab) == sp) && (!ss || side(S, lab) == ss) && c.size() < 3) c.push_back(lab);
+        if (c.size() == 3) {
+          best = c;
+          best_w = w;
+        }
+      }
+    return best;
   }
 
   // Matrix product in bit-scattered mode: operands are read in their stored

@@ -81,8 +81,11 @@ def summarize_traffic(run_dir):
     import glob
     import sqlite3
 
-    def per_dispatch(tag, counter):
-        """[(kernel name, value)] for every dispatch inside a contract call (k_block_init .. k_block_finish)."""
+    def per_dispatch(tag, counter, kernel=None):
+        """[(kernel name, value)] for every dispatch of the copy run, or, with ``kernel``, for every dispatch
+        of that kernel in the last contract call that launches it (the dispatches after one call's
+        k_block_finish up to the next one's): the timed call of that precision, after the warm-up call
+        that ran the tile autotuner."""
         dbs = glob.glob(os.path.join(run_dir, tag, "**", "*results.db"), recursive=True)
         rows = []
         for db in dbs:
@@ -90,15 +93,17 @@ def summarize_traffic(run_dir):
             rows += con.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
                                 "where counter_name = ? group by dispatch_id order by dispatch_id", (counter,)).fetchall()
         rows.sort()
-        out, inside = [], False
+        if kernel is None:
+            return [(name, val) for _, name, val in rows]
+        calls, cur = [], []
         for _, name, val in rows:
-            if "k_block_init" in name:
-                inside = True
-            elif "k_block_finish" in name:
-                inside = False
-            elif inside or tag.startswith("copy"):
-                out.append((name, val))
-        return out
+            if "k_block_finish" in name:
+                if cur:
+                    calls.append(cur)
+                cur = []
+            elif f"qx::{kernel}<" in name:
+                cur.append((name, val))
+        return calls[-1] if calls else []
 
     cal = {}
     for counter, tag in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
@@ -107,9 +112,9 @@ def summarize_traffic(run_dir):
         cal[counter] = {"kernel": name[:80], "kib": val, "scale": COPY_BYTES / (val * 1024.0)}
     kernels = {}
     for short in KERNEL_NAMES.values():
-        f = [v for v in per_dispatch("bench_fetch", "FETCH_SIZE") if f"qx::{short}<" in v[0]]
-        w = [v for v in per_dispatch("bench_write", "WRITE_SIZE") if f"qx::{short}<" in v[0]]
-        if not f or not w:
+        f = per_dispatch("bench_fetch", "FETCH_SIZE", short)
+        w = per_dispatch("bench_write", "WRITE_SIZE", short)
+        if not f or len(f) != len(w):
             continue
         fb = sum(v for _, v in f) / len(f) * 1024.0 * cal["FETCH_SIZE"]["scale"]
         wb = sum(v for _, v in w) / len(w) * 1024.0 * cal["WRITE_SIZE"]["scale"]
@@ -119,16 +124,17 @@ def summarize_traffic(run_dir):
     lines = ["# HBM traffic of the matrix-product kernels, c2 (30-qubit 5x6 grid, depth 12, 1024 slices, 256 bitstrings)",
              "",
              "Two counter passes over one timed `bench.py` step of each precision (every launch of each kernel inside",
-             "the contract call, autotuning trials excluded), each scaled by the same counter read on a plain 1 GiB",
+             "the timed contract call; the warm-up call before it runs the tile autotuner), each scaled by the same",
+             "counter read on a plain 1 GiB",
              "device copy (`bench.py --copy-calibration`):",
              "",
              "```",
              "cd /tmp && export TMPDIR=/tmp",
              "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/traffic/copy_fetch -- python3 $R/bench.py --copy-calibration",
              "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/traffic/copy_write -- python3 $R/bench.py --copy-calibration",
-             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/traffic/bench_fetch -- python3 $R/bench.py --steps 1 --warmup 0 "
+             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/traffic/bench_fetch -- python3 $R/bench.py --steps 1 --warmup 1 "
              "--no-cpu-baseline --no-permute",
-             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/traffic/bench_write -- python3 $R/bench.py --steps 1 --warmup 0 "
+             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/traffic/bench_write -- python3 $R/bench.py --steps 1 --warmup 1 "
              "--no-cpu-baseline --no-permute",
              "python3 $R/bench.py --summarize-traffic $R/gpurun_out/traffic",
              "```",
@@ -424,7 +430,8 @@ def main():
             ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
             r["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
                              "unit": "TFLOP/s", "frac": ach / PEAKS[precision],
-                             "traffic": measured_traffic(KERNEL_NAMES[precision]),
+                             # counters were taken on the 30-qubit workload only
+                             "traffic": measured_traffic(KERNEL_NAMES[precision]) if args.workload == "c2" else None,
                              "kernel": KERNEL_NAMES[precision],
                              "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
                              "launches_per_step": g["launches"] / args.steps,

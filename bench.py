@@ -238,6 +238,12 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def refined_note(args):
+    cost = f"roofline cost, {args.mem_weight:g} flops per element moved" if args.mem_weight else "flop cost"
+    return (f"; tree refined by local sub-tree re-ordering ({cost}) of the best {args.reconfigure} greedy trials"
+            if args.reconfigure else "")
+
+
 def c4_bench(args):
     """c4: a contiguous block of slices of the 49-qubit network for one bitstring."""
     import torch
@@ -246,7 +252,7 @@ def c4_bench(args):
 
     torch.cuda.set_device(0)
     w = configs.get("c4")
-    tree, sliced, st = w.plan_inputs()
+    tree, sliced, st = w.plan_inputs(reconfigure=args.reconfigure, mem_weight=args.mem_weight)
     xs = w.bitstrings()
     x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
     plan = qxtn.Plan(w.network(), tree, sliced, precision=args.precision, max_bitstrings=1,
@@ -266,7 +272,7 @@ def c4_bench(args):
     out = {"metric": "slices/s + complex TFLOP/s (49-qubit block)", "value": n / el, "unit": "slices/s",
            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": DTYPES[args.precision],
            "data": "synthetic (seeded circuit and bitstring)",
-           "config": {"workload": f"c4: {w.description}", "slices_timed": n, "slice_batch": bsz,
+           "config": {"workload": f"c4: {w.description}{refined_note(args)}", "slices_timed": n, "slice_batch": bsz,
                       "tree_width": st["width"], "flops_per_slice": st["flops_per_slice"]},
            "seconds": el, "complex_tflops": flops / el / 1e12,
            "frac_of_peak": flops / el / PEAKS[args.precision],
@@ -351,6 +357,11 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison run")
     ap.add_argument("--no-permute", action="store_true", help="skip the standalone permute measurement")
     ap.add_argument("--slices", type=int, default=4096, help="c4: contiguous slices timed")
+    ap.add_argument("--reconfigure", type=int, default=0, metavar="R",
+                    help="c2/c4: refine the best R greedy trees by local sub-tree re-ordering "
+                         "(a different, cheaper tree than the config's greedy one)")
+    ap.add_argument("--mem-weight", type=float, default=16.0,
+                    help="with --reconfigure: flop:element ratio of the roofline cost (0 = flops only)")
     ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
     ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
@@ -385,7 +396,7 @@ def main():
     from workloads import configs
 
     w = configs.get(args.workload)
-    tree, sliced, st = w.plan_inputs()
+    tree, sliced, st = w.plan_inputs(reconfigure=args.reconfigure, mem_weight=args.mem_weight)
     xs = w.bitstrings()
     B = len(xs)
     net = w.network()
@@ -431,7 +442,8 @@ def main():
             r["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
                              "unit": "TFLOP/s", "frac": ach / PEAKS[precision],
                              # counters were taken on the 30-qubit workload only
-                             "traffic": measured_traffic(KERNEL_NAMES[precision]) if args.workload == "c2" else None,
+                             "traffic": (measured_traffic(KERNEL_NAMES[precision])
+                                         if args.workload == "c2" and not args.reconfigure else None),
                              "kernel": KERNEL_NAMES[precision],
                              "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
                              "launches_per_step": g["launches"] / args.steps,
@@ -453,7 +465,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPES[args.precision],
         "data": "synthetic (seeded random circuit, planner and bitstrings; no external dataset)",
-        "config": {"workload": f"{w.name}: {w.description}", "precision": args.precision,
+        "config": {"workload": f"{w.name}: {w.description}{refined_note(args)}", "precision": args.precision,
                    "qubits": w.n_qubits, "depth": w.depth, "slices": n_slices, "bitstrings": B,
                    "slice_batch": main["slice_batch"], "tree_width": st["width"],
                    "flops_per_slice_amplitude": st["flops_per_slice"]},

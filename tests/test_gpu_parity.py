@@ -262,3 +262,20 @@ def test_dense_leaves_as_matrix_product_operands(precision, order, sliced, js):
     got = gpu_amplitudes(plan, xs)
     want = oracle.amplitudes_sliced(net, CHAIN_TREE, xs, list(sliced))
     assert rms_err(got, want) < (TOL_C64 if precision == "c64" else TOL_SPLIT)
+
+
+@pytest.mark.parametrize("mem_weight", [0.0, 16.0])
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT)])
+def test_reconfigured_tree_against_statevector(precision, tol, mem_weight):
+    # a tree refined by local sub-tree re-ordering (cheaper, different shapes) gives the same amplitudes
+    from workloads import plan_network
+    circ = random_grid_circuit(4, 4, 10, 61)
+    net = circuit_to_network(circ)
+    tree0, _, st0 = plan_network(net, 3, trials=4, seed=62)
+    tree, sl, st = plan_network(net, 3, trials=4, seed=62, reconfigure=2, mem_weight=mem_weight)
+    assert st["total_flops"] < st0["total_flops"] and not np.array_equal(tree, tree0)
+    xs = random_bitstrings(16, 64, 63)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), precision=precision)
+    got = gpu_amplitudes(plan, xs)
+    want = oracle.amplitudes_statevector(circ, xs)
+    assert rms_err(got, want) < tol

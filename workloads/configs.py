@@ -47,12 +47,16 @@ class Workload:
             self._cache["net"] = circuit_to_network(self.circuit())
         return self._cache["net"]
 
-    def plan_inputs(self):
-        """(tree, sliced_labels, stats) from the seeded planner."""
-        if "plan" not in self._cache:
-            self._cache["plan"] = plan_network(self.network(), self.n_sliced, trials=self.planner_trials,
-                                               seed=self.planner_seed, width_cap=self.width_cap)
-        return self._cache["plan"]
+    def plan_inputs(self, reconfigure=0, mem_weight=0.0):
+        """(tree, sliced_labels, stats) from the seeded planner; ``reconfigure`` = r > 0 refines the
+        best r greedy trials by local sub-tree re-ordering under a flop (``mem_weight`` 0) or
+        roofline cost (the configs themselves use the greedy tree)."""
+        key = ("plan", reconfigure, mem_weight)
+        if key not in self._cache:
+            self._cache[key] = plan_network(self.network(), self.n_sliced, trials=self.planner_trials,
+                                            seed=self.planner_seed, width_cap=self.width_cap,
+                                            reconfigure=reconfigure, mem_weight=mem_weight)
+        return self._cache[key]
 
     def bitstrings(self, count=None):
         return random_bitstrings(self.n_qubits, count or self.n_bitstrings, self.bitstring_seed)

@@ -2,7 +2,7 @@
 // contraction (Sec. III-B: slicing, permuting, contracting, recombination).
 //
 //   k_simt      small / memory-bound pairwise contraction, any bit layout
-//   k_dot       long inner products (the root of a slice's tree)
+//   k_dot       long inner products (the root of a slice's tree); k_dot_wave for K <= 16384
 //   k_permute   LDS-tiled index permutation of dim-2 tensors
 //   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)
@@ -166,6 +166,47 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
                 (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
     if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, r);
     else p.c[(int64_t)item * p.c_item + o] = r;
+  }
+}
+
+// Shorter inner products (K <= 16384): one wavefront per output, four outputs
+// per work-group, reduced with cross-lane shuffles only (no LDS, no barrier).
+// A lane keeps four partial sums of at most K / 256 terms each.
+__global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= ((int64_t)1 << p.n_out)) return;  // whole waves only; nothing below waits for others
+  const int item = blockIdx.y;
+  int64_t ao = (int64_t)item * p.a_item + (p.a_gather ? p.a_gather[item] : 0);
+  int64_t bo = (int64_t)item * p.b_item + (p.b_gather ? p.b_gather[item] : 0);
+#pragma unroll
+  for (int i = 0; i < QX_MAX_BITS; ++i)
+    if (i < p.n_out && ((o >> i) & 1)) { ao += p.a_os[i]; bo += p.b_os[i]; }
+  const QxCplx* __restrict__ A = p.a + ao;
+  const QxCplx* __restrict__ B = p.b + bo;
+  QxCplx acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f}, acc2 = {0.f, 0.f}, acc3 = {0.f, 0.f};
+  const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (p.K & 3) == 0;
+  if (vec) {
+    for (int64_t k = 4 * (int64_t)lane; k < p.K; k += 256) {
+      const v4f a0 = *(const v4f*)(A + k), a1 = *(const v4f*)(A + k + 2);
+      const v4f b0 = *(const v4f*)(B + k), b1 = *(const v4f*)(B + k + 2);
+      acc0 = cmul_acc(acc0, QxCplx{a0[0], a0[1]}, QxCplx{b0[0], b0[1]});
+      acc1 = cmul_acc(acc1, QxCplx{a0[2], a0[3]}, QxCplx{b0[2], b0[3]});
+      acc2 = cmul_acc(acc2, QxCplx{a1[0], a1[1]}, QxCplx{b1[0], b1[1]});
+      acc3 = cmul_acc(acc3, QxCplx{a1[2], a1[3]}, QxCplx{b1[2], b1[3]});
+    }
+  } else {
+    for (int64_t k = lane; k < p.K; k += 64) acc0 = cmul_acc(acc0, A[k], B[k]);
+  }
+  QxCplx acc = {(acc0.x + acc1.x) + (acc2.x + acc3.x), (acc0.y + acc1.y) + (acc2.y + acc3.y)};
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (lane == 0) {
+    if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc);
+    else p.c[(int64_t)item * p.c_item + o] = acc;
   }
 }
 
@@ -363,8 +404,13 @@ int gemm_default_tile(int64_t M, int64_t N) {
 }
 
 hipError_t launch_dot(const DotArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)(1LL << a.n_out), (unsigned)a.n_items);
-  hipLaunchKernelGGL(k_dot, grid, dim3(256), 0, s, a);
+  if (a.K <= 16384) {
+    dim3 grid((unsigned)(((1LL << a.n_out) + 3) / 4), (unsigned)a.n_items);
+    hipLaunchKernelGGL(k_dot_wave, grid, dim3(256), 0, s, a);
+  } else {
+    dim3 grid((unsigned)(1LL << a.n_out), (unsigned)a.n_items);
+    hipLaunchKernelGGL(k_dot, grid, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

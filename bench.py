@@ -240,8 +240,12 @@ def serve_bench(args):
 
 def refined_note(args):
     cost = f"roofline cost, {args.mem_weight:g} flops per element moved" if args.mem_weight else "flop cost"
-    return (f"; tree refined by local sub-tree re-ordering ({cost}) of the best {args.reconfigure} greedy trials"
+    note = (f"; tree refined by local sub-tree re-ordering ({cost}) of the best {args.reconfigure} greedy trials"
             if args.reconfigure else "")
+    if getattr(args, "open_qubits", 0):
+        note += (f"; {args.open_qubits} highest-numbered qubits left open "
+                 f"({1 << args.open_qubits} amplitudes per bitstring)")
+    return note
 
 
 def c4_bench(args):
@@ -360,6 +364,8 @@ def main():
     ap.add_argument("--reconfigure", type=int, default=0, metavar="R",
                     help="c2/c4: refine the best R greedy trees by local sub-tree re-ordering "
                          "(a different, cheaper tree than the config's greedy one)")
+    ap.add_argument("--open-qubits", type=int, default=0, metavar="M",
+                    help="c2: leave the M highest-numbered qubits open (2^M amplitudes per bitstring)")
     ap.add_argument("--mem-weight", type=float, default=16.0,
                     help="with --reconfigure: flop:element ratio of the roofline cost (0 = flops only)")
     ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
@@ -387,6 +393,9 @@ def main():
     if args.workload == "c5":
         serve_bench(args)
         return
+    if args.open_qubits and args.workload != "c2":
+        print("bench.py: --open-qubits applies to the c2 workload only", file=sys.stderr)
+        sys.exit(2)
     if args.workload == "c4":
         c4_bench(args)
         return
@@ -403,13 +412,16 @@ def main():
     torch.cuda.set_device(0)
     x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
     n_slices = 1 << len(sliced)
+    # open output qubits: the highest-numbered ones; each bitstring then yields 2^m amplitudes
+    open_q = list(range(w.n_qubits - args.open_qubits, w.n_qubits))
+    per_x = 1 << args.open_qubits
 
     def run(precision):
         """Plan, warm up, then time exactly args.steps full contractions."""
         plan = qxtn.Plan(net, tree, sliced, precision=precision, max_bitstrings=B,
-                         autotune=not args.no_autotune)
+                         autotune=not args.no_autotune, open_qubits=open_q)
         info = plan.info()
-        amp = torch.zeros((B, 2), dtype=torch.float64, device="cuda")
+        amp = torch.zeros((B, per_x, 2), dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             plan.contract(x, amp)
         torch.cuda.synchronize()
@@ -432,7 +444,7 @@ def main():
             plan.set_timing(False)
         lat = np.array([s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)])
         executed = info["flops_block"] * (n_slices >> info["slice_batch_log2"]) + info["flops_call"]
-        r = {"value": B * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+        r = {"value": B * per_x * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
              "complex_tflops": executed / (elapsed / args.steps) / 1e12,
              "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
              "slice_batch": 1 << info["slice_batch_log2"]}
@@ -443,7 +455,8 @@ def main():
                              "unit": "TFLOP/s", "frac": ach / PEAKS[precision],
                              # counters were taken on the 30-qubit workload only
                              "traffic": (measured_traffic(KERNEL_NAMES[precision])
-                                         if args.workload == "c2" and not args.reconfigure else None),
+                                         if args.workload == "c2" and not args.reconfigure
+                                         and not args.open_qubits else None),
                              "kernel": KERNEL_NAMES[precision],
                              "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
                              "launches_per_step": g["launches"] / args.steps,
@@ -467,6 +480,7 @@ def main():
         "data": "synthetic (seeded random circuit, planner and bitstrings; no external dataset)",
         "config": {"workload": f"{w.name}: {w.description}{refined_note(args)}", "precision": args.precision,
                    "qubits": w.n_qubits, "depth": w.depth, "slices": n_slices, "bitstrings": B,
+                   "open_qubits": args.open_qubits,
                    "slice_batch": main["slice_batch"], "tree_width": st["width"],
                    "flops_per_slice_amplitude": st["flops_per_slice"]},
         "complex_tflops": main["complex_tflops"],
@@ -514,10 +528,12 @@ def main():
         scale = np.sqrt(np.mean(np.abs(ref) ** 2))
 
         def err(pl):
-            a0 = torch.zeros((k, 2), dtype=torch.float64, device="cuda")
+            a0 = torch.zeros((k, per_x, 2), dtype=torch.float64, device="cuda")
             pl.contract(x[:k], a0, (0, 1))
             torch.cuda.synchronize()
-            got = a0.cpu().numpy()
+            # with open qubits, the value whose open bits equal the bitstring's own is the closed amplitude
+            own = [sum(((int(xs[b]) >> q) & 1) << i for i, q in enumerate(open_q)) for b in range(k)]
+            got = a0.cpu().numpy()[np.arange(k), own]
             got = got[:, 0] + 1j * got[:, 1]
             return {"slice": 0, "bitstrings": k, "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
 

@@ -84,6 +84,10 @@ typedef struct {
   int32_t eager;               /* non-zero: launch every op of every slice block individually;
                                   0: capture one block's ops in a HIP graph per batch size and
                                   replay it for every block (always eager while timing is on) */
+  uint64_t open_qubits;        /* bit q set: qubit q's output wire stays open, so each bitstring
+                                  yields the 2^m amplitudes of all values of those m qubits
+                                  (Sec. II: output indices left open give a batch of amplitudes);
+                                  m <= 16 and max_bitstrings * 2^m <= 2^24.  0 = all closed */
 } qx_plan_options;
 
 typedef struct {
@@ -101,6 +105,8 @@ typedef struct {
   double flops_block;          /* complex flops executed per slice block at max_bitstrings */
   double gemm_flops_block;     /* of which on matrix cores */
   double flops_call;           /* complex flops executed once per call */
+  int32_t n_open;              /* m: open output qubits (amplitudes per bitstring = 2^m) */
+  int32_t reserved;
 } qx_plan_info;
 
 typedef struct qx_plan qx_plan;
@@ -118,7 +124,7 @@ typedef struct qx_plan qx_plan;
  *                  or earlier steps.  The last step is the root.
  *   sliced         host int64 [n_sliced] labels to slice; none may be an output
  *                  wire; n_sliced <= 40.
- *   opt            host; NULL = defaults (QX_C64, max_bitstrings 1, auto, 0, 0, 0, 0).
+ *   opt            host; NULL = defaults (QX_C64, max_bitstrings 1, auto, 0, 0, 0, 0, 0).
  *   stream         hipStream_t used for uploads and pre-contraction.
  *   out            receives the plan (owned by the caller; free with qx_plan_destroy).
  */
@@ -133,6 +139,9 @@ qx_status qx_plan_get_info(const qx_plan *plan, qx_plan_info *info);
  * Accumulate amplitudes: for each of the B bitstrings x_b,
  *   d_amplitudes[b] += sum over slices s in [slice_begin, slice_end) of the value
  *                      of slice s's network closed by x_b        (Eq. 2, Sec. II)
+ * With m open qubits q_0 < ... < q_{m-1} the network is closed by x_b on the
+ * other qubits only and d_amplitudes[b][j] receives the amplitude of x_b with
+ * qubit q_i set to bit i of j (x_b's own bits at open qubits are ignored).
  * Per-slice values are formed in FP32 complex; the sum over slices and the
  * accumulation are FP64, in ascending slice order, so the result is bitwise
  * reproducible for a given plan, range and B.
@@ -140,7 +149,8 @@ qx_status qx_plan_get_info(const qx_plan *plan, qx_plan_info *info);
  *   d_bitstrings   device uint64 [B].
  *   B              1..max_bitstrings.
  *   slice range    0 <= slice_begin <= slice_end <= 2^n_sliced (empty is a no-op).
- *   d_amplitudes   device double [B][2] (re, im), caller-zeroed, ACCUMULATED (+=).
+ *   d_amplitudes   device double [B][2^m][2] (re, im), caller-zeroed, ACCUMULATED (+=);
+ *                  m = 0 unless the plan has open qubits.  Its size is not checked here.
  *   stream         all work is enqueued on it; the call does not synchronise.
  * Calls on one plan must not overlap in time (the plan's arena is shared):
  * serialise them on one stream.  Caller buffers must stay alive until the

@@ -71,7 +71,7 @@ struct qx_plan {
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // per batch size
 };
 
-static int64_t state_bytes(const PlanCore& pc) { return 64 + (int64_t)pc.max_b * 16; }
+static int64_t state_bytes(const PlanCore& pc) { return 64 + ((int64_t)pc.max_b << pc.n_open) * 16; }
 
 static int64_t misc_bytes(const PlanCore& pc) {
   return ((int64_t)pc.n_scale_slots + ABSMAX_PARTIALS + 64) * 4;
@@ -245,10 +245,12 @@ static qx_status run_block(qx_plan* p, int B, hipStream_t s) {
   sa.root_item = rt.batched ? rt.elems() : 0;
   sa.root_gather = gather_ptr(p, pc.root_gather);
   sa.amp = ba.acc;
-  sa.n_items = B;
+  sa.n_items = B << pc.n_open;
   sa.n_sbits = pc.js;
   for (int j = 0; j < pc.js; ++j) sa.s_stride[j] = pc.root_sstride[j];
-  const double sbytes = 8.0 * std::ldexp(1.0, pc.js) * B + 32.0 * B;
+  sa.n_obits = pc.n_open;
+  for (int i = 0; i < pc.n_open; ++i) sa.o_stride[i] = pc.root_ostride[i];
+  const double sbytes = (8.0 * std::ldexp(1.0, pc.js) + 32.0) * ((int64_t)B << pc.n_open);
   e = timed(p, QX_OPCLASS_SLICESUM, 0.0, sbytes, s, [&] { return launch_slice_sum(sa, s); });
   if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("slice-sum launch: ") + hipGetErrorString(e));
   return QX_OK;
@@ -338,7 +340,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     const int64_t r = net->index_ptr[t + 1] - net->index_ptr[t];
     if (r < 0 || r > 40) return fail(QX_ERR_UNSUPPORTED, "tensor rank must be in 0..40");
   }
-  qx_plan_options opt = {QX_C64, 1, -1, 0, 0, 0, 0};
+  qx_plan_options opt = {QX_C64, 1, -1, 0, 0, 0, 0, 0};
   if (opt_in) opt = *opt_in;
   if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
     return fail(QX_ERR_INVALID_ARG, "unknown precision");
@@ -347,6 +349,12 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
   if (opt.slice_batch_log2 < -1 || opt.slice_batch_log2 > std::min(n_sliced, QX_MAX_SBITS))
     return fail(QX_ERR_INVALID_ARG, "slice_batch_log2 must be -1 or in 0..min(n_sliced, 24)");
   if (opt.hbm_budget_bytes < 0) return fail(QX_ERR_INVALID_ARG, "hbm_budget_bytes < 0");
+  if (net->n_qubits < 64 && (opt.open_qubits >> net->n_qubits) != 0)
+    return fail(QX_ERR_INVALID_ARG, "open_qubits names a qubit >= n_qubits");
+  const int n_open = __builtin_popcountll(opt.open_qubits);
+  if (n_open > QX_MAX_OBITS) return fail(QX_ERR_UNSUPPORTED, "at most 16 open qubits");
+  if (((int64_t)opt.max_bitstrings << n_open) > ((int64_t)1 << 24))
+    return fail(QX_ERR_UNSUPPORTED, "max_bitstrings * 2^(open qubits) must be <= 2^24");
 
   qx_plan* p = new (std::nothrow) qx_plan();
   if (!p) return fail(QX_ERR_INVALID_ARG, "out of host memory");
@@ -487,6 +495,8 @@ qx_status qx_plan_get_info(const qx_plan* p, qx_plan_info* info) {
   info->flops_block = pc.flops_block;
   info->gemm_flops_block = pc.gemm_flops_block;
   info->flops_call = pc.flops_call;
+  info->n_open = pc.n_open;
+  info->reserved = 0;
   return QX_OK;
 }
 
@@ -536,7 +546,7 @@ qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64
   ba.slice_begin = slice_begin;
   ba.slice_end = slice_end;
   ba.js = pc.js;
-  ba.n_items = B;
+  ba.n_items = B << pc.n_open;  // accumulated values
   HIP_TRY(launch_block_init(ba, s));
   const bool use_graph = !p->eager && !p->timing && last > first;
   hipGraphExec_t exec = nullptr;

@@ -16,6 +16,7 @@
 #define QX_MAX_KBITS 24     // contracted bits of one small contraction
 #define QX_MAX_HBITS 16     // shared slice bits of one matrix product (batch)
 #define QX_MAX_SBITS 24     // slice bits carried to the root
+#define QX_MAX_OBITS 16     // open output qubits (amplitudes per bitstring = 2^m)
 
 struct QxCplx { float x, y; };
 
@@ -114,10 +115,12 @@ struct SliceSumArgs {
   const int64_t *block;                 // if set, the slice range is block[1], block[2]
   int64_t root_item;
   const int64_t *root_gather;
-  double *amp;                          // [items][2]
-  int32_t n_items, n_sbits;
+  double *amp;                          // [items][2^n_obits][2]
+  int32_t n_items, n_sbits;             // n_items counts values: bitstrings << n_obits
   int32_t s_lo, s_hi;
   int64_t s_stride[QX_MAX_SBITS];
+  int32_t n_obits, pad_;                // open output qubits: value j's bit i selects o_stride[i]
+  int64_t o_stride[QX_MAX_OBITS];
 };
 
 // Largest magnitude of a tensor -> power-of-two scale for FP16 operands:
@@ -138,7 +141,8 @@ struct AbsmaxArgs {
 // state[4], state[5] the call's slice range, state[6] log2 slices per block.
 struct BlockArgs {
   int64_t *state;
-  double *acc;                          // [n_items][2] FP64 accumulator (zeroed by k_block_init)
+  double *acc;                          // [n_items][2] FP64 accumulator (zeroed by k_block_init);
+                                        // n_items counts values: bitstrings << open qubits
   int64_t first_block, slice_begin, slice_end;
   int32_t js, n_items;
 };

@@ -268,11 +268,17 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 
 // ---------------------------------------------------------------------------
 // FP64 sum over the slices of one block, ascending slice order (deterministic).
+// One thread per value: bitstring v >> n_obits, open-qubit assignment j = the
+// low n_obits bits of v.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_slice_sum(SliceSumArgs p) {
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= p.n_items) return;
-  const int64_t base = (int64_t)item * p.root_item + (p.root_gather ? p.root_gather[item] : 0);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= p.n_items) return;
+  const int item = v >> p.n_obits;
+  int64_t base = (int64_t)item * p.root_item + (p.root_gather ? p.root_gather[item] : 0);
+#pragma unroll
+  for (int i = 0; i < QX_MAX_OBITS; ++i)
+    if (i < p.n_obits && ((v >> i) & 1)) base += p.o_stride[i];
   const int lo = p.block ? (int)p.block[1] : p.s_lo, hi = p.block ? (int)p.block[2] : p.s_hi;
   double sr = 0.0, si = 0.0;
   for (int s = lo; s < hi; ++s) {
@@ -284,8 +290,8 @@ __global__ __launch_bounds__(256) void k_slice_sum(SliceSumArgs p) {
     sr += (double)v.x;
     si += (double)v.y;
   }
-  p.amp[2 * item] += sr;
-  p.amp[2 * item + 1] += si;
+  p.amp[2 * (int64_t)v] += sr;
+  p.amp[2 * (int64_t)v + 1] += si;
 }
 
 constexpr int ABSMAX_GRID = 1024;

@@ -714,6 +714,17 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
     pc.kind[it->second] = KIND_SLICE;
     pc.aux[it->second] = j;
   }
+  // open output qubits: their wires become regular indices that no contraction sums, so they
+  // reach the root, which then holds 2^m values per bitstring
+  pc.open_bit.assign(L, -1);
+  pc.n_open = 0;
+  for (int qb = 0; qb < net->n_qubits; ++qb)
+    if ((opt.open_qubits >> qb) & 1ULL) {
+      const int d = id.find(net->output_index[qb])->second;
+      pc.kind[d] = KIND_REG;
+      pc.aux[d] = -1;
+      pc.open_bit[d] = pc.n_open++;
+    }
   // tree validity: SSA, each id consumed once, all consumed
   std::vector<char> used(2 * n - 1, 0);
   for (int t = 0; t < n - 1; ++t) {
@@ -841,11 +852,13 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
   {
     const Tensor& r = pc.tensors[pc.root];
     pc.root_sstride.assign(js, 0);
+    pc.root_ostride.assign(pc.n_open, -1);
     GatherDesc g;
     g.tensor = pc.root;
     for (size_t i = 0; i < r.lay.size(); ++i) {
       const int lab = r.lay[i];
       if (pc.kind[lab] == KIND_SLICE && pc.aux[lab] < js) pc.root_sstride[pc.aux[lab]] = (int64_t)1 << i;
+      else if (pc.open_bit[lab] >= 0) pc.root_ostride[pc.open_bit[lab]] = (int64_t)1 << i;
       else if (pc.kind[lab] == KIND_OUT && !r.batched) {
         g.q.push_back(pc.aux[lab]);
         g.stride.push_back((int64_t)1 << i);
@@ -857,6 +870,11 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
     for (int j = 0; j < js; ++j)
       if (pc.root_sstride[j] == 0) {
         err = "internal: a varying sliced index does not reach the root";
+        return QX_ERR_INVALID_TREE;
+      }
+    for (int i = 0; i < pc.n_open; ++i)
+      if (pc.root_ostride[i] < 0) {
+        err = "internal: an open output qubit does not reach the root";
         return QX_ERR_INVALID_TREE;
       }
     if (!g.q.empty()) {

@@ -76,6 +76,8 @@ struct PlanCore {
   std::vector<int64_t> label_of;       // dense label id -> user label
   std::vector<int> kind;               // per label id: 0 regular, 1 output, 2 sliced
   std::vector<int> aux;                // qubit (output) or slice index j (sliced)
+  std::vector<int> open_bit;           // per label id: bit i of the open-qubit value index, or -1
+  int n_open = 0;                      // open output qubits m (a regular index each, up to the root)
   std::vector<int> aux_label_id;       // dense label id of every index entry of the network
   std::vector<double> leaf_data;       // complex128 interleaved, leaf pool order
   int64_t leaf_pool_elems = 0;
@@ -87,6 +89,7 @@ struct PlanCore {
   int root = -1;                       // tensor id of the root
   int root_gather = -1;
   std::vector<int64_t> root_sstride;   // stride of varying sliced index j in the root
+  std::vector<int64_t> root_ostride;   // stride of open-qubit bit i in the root
   int64_t arena_bytes = 0;
   int width = 0;
   double flops_per_slice = 0, flops_block = 0, gemm_flops_block = 0, flops_call = 0;

@@ -50,7 +50,8 @@ class _Network(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_bitstrings", C.c_int32),
                 ("slice_batch_log2", C.c_int32), ("dry_run", C.c_int32),
-                ("hbm_budget_bytes", C.c_int64), ("autotune", C.c_int32), ("eager", C.c_int32)]
+                ("hbm_budget_bytes", C.c_int64), ("autotune", C.c_int32), ("eager", C.c_int32),
+                ("open_qubits", C.c_uint64)]
 
 
 class PlanInfo(C.Structure):
@@ -59,7 +60,7 @@ class PlanInfo(C.Structure):
                 ("n_ops_const", C.c_int32), ("n_ops_call", C.c_int32), ("n_ops_block", C.c_int32),
                 ("n_gemm_block", C.c_int32), ("flops_per_slice", C.c_double),
                 ("flops_block", C.c_double), ("gemm_flops_block", C.c_double),
-                ("flops_call", C.c_double)]
+                ("flops_call", C.c_double), ("n_open", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -132,7 +133,7 @@ class Plan:
     """Owns a qx_plan handle (qx_plan_create / qx_plan_destroy)."""
 
     def __init__(self, network, tree, sliced=(), precision="c64", max_bitstrings=1, slice_batch_log2=-1,
-                 dry_run=False, hbm_budget_bytes=0, autotune=False, eager=False, stream=None):
+                 dry_run=False, hbm_budget_bytes=0, autotune=False, eager=False, open_qubits=(), stream=None):
         index_ptr, index_ids, data_ptr, data, output_index = network.to_csr()
         self._keep = [np.ascontiguousarray(index_ptr, np.int64), np.ascontiguousarray(index_ids, np.int64),
                       np.ascontiguousarray(data_ptr, np.int64), np.ascontiguousarray(data, np.float64),
@@ -143,8 +144,11 @@ class Plan:
         tr = np.ascontiguousarray(np.asarray(tree, dtype=np.int32).reshape(-1))
         sl = np.ascontiguousarray(np.asarray(list(sliced), dtype=np.int64))
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        mask = 0
+        for q in open_qubits:
+            mask |= 1 << int(q)
         opt = _Options(prec, int(max_bitstrings), int(slice_batch_log2), int(bool(dry_run)), int(hbm_budget_bytes),
-                       int(bool(autotune)), int(bool(eager)))
+                       int(bool(autotune)), int(bool(eager)), mask)
         h = C.c_void_p()
         _check(lib().qx_plan_create(C.byref(net), _ptr(tr, C.c_int32) if tr.size else None,
                                     _ptr(sl, C.c_int64) if sl.size else None, len(sl), C.byref(opt),
@@ -154,6 +158,7 @@ class Plan:
         self.n_qubits = len(oi)
         self.max_bitstrings = int(max_bitstrings)
         self.precision = prec
+        self.n_open = bin(mask).count("1")
         self._keep = None
 
     def info(self) -> dict:
@@ -162,9 +167,14 @@ class Plan:
         return inf.as_dict()
 
     def contract(self, bitstrings, amplitudes, slice_range=None, stream=None):
-        """amplitudes (float64 [B, 2], device) += sum over slice_range of each slice's value."""
+        """amplitudes (float64 [B, 2^m, 2] contiguous, device; m open qubits, [B, 2] when none)
+        += sum over slice_range of each slice's value."""
         lo, hi = slice_range if slice_range is not None else (0, 1 << self.n_sliced)
         B = int(bitstrings.shape[0])
+        need = (B << self.n_open) * 2
+        if amplitudes.numel() < need or not amplitudes.is_contiguous() or amplitudes.element_size() != 8:
+            raise ValueError(f"amplitudes must be a contiguous float64 buffer of at least B * 2^{self.n_open} * 2 "
+                             "elements")
         _check(lib().qx_contract(self.handle, C.c_void_p(bitstrings.data_ptr()), B, int(lo), int(hi),
                                  C.c_void_p(amplitudes.data_ptr()), _stream_handle(stream)))
 

@@ -66,6 +66,15 @@ def test_contract_on_dry_run_plan_is_refused():
         def data_ptr(self):
             return 1024
 
+        def numel(self):
+            return 2
+
+        def is_contiguous(self):
+            return True
+
+        def element_size(self):
+            return 8
+
     with pytest.raises(qxtn.QxError) as e:
         p.contract(_T(), _T())
     assert e.value.status == qxtn.QX_ERR_DRY_RUN
@@ -143,3 +152,49 @@ def test_error_message_is_set():
     except qxtn.QxError:
         pass
     assert "output wire" in qxtn.last_error()
+
+
+def test_open_qubits_plans_and_limits():
+    net, tree, sl = _small()
+    base = qxtn.Plan(net, tree, sl, max_bitstrings=4, dry_run=True).info()
+    p = qxtn.Plan(net, tree, sl, max_bitstrings=4, open_qubits=(0, 4), dry_run=True)
+    inf = p.info()
+    assert inf["n_open"] == 2 and base["n_open"] == 0
+    assert inf["flops_per_slice"] >= base["flops_per_slice"]
+    # every qubit open: one contraction gives the whole state
+    allq = qxtn.Plan(net, tree, sl, max_bitstrings=1, open_qubits=range(6), dry_run=True).info()
+    assert allq["n_open"] == 6
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn.Plan(net, tree, sl, open_qubits=(6,), dry_run=True))
+    big = circuit_to_network(ghz_circuit(20))
+    _expect(qxtn.QX_ERR_UNSUPPORTED,
+            lambda: qxtn.Plan(big, greedy_tree(big), [], open_qubits=range(17), dry_run=True))
+    _expect(qxtn.QX_ERR_UNSUPPORTED,
+            lambda: qxtn.Plan(big, greedy_tree(big), [], max_bitstrings=1 << 10, open_qubits=range(15),
+                              dry_run=True))
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the binding's ctypes structures must have the header's sizes and field offsets
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"qx_plan_options": qxtn._Options, "qx_plan_info": qxtn.PlanInfo, "qx_network": qxtn._Network}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qxtn.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)

@@ -279,3 +279,56 @@ def test_reconfigured_tree_against_statevector(precision, tol, mem_weight):
     got = gpu_amplitudes(plan, xs)
     want = oracle.amplitudes_statevector(circ, xs)
     assert rms_err(got, want) < tol
+
+
+def _with_open_bits(xs, open_q):
+    """Every bitstring with its open qubits replaced by each assignment j (bit i of j -> qubit open_q[i])."""
+    mask = sum(1 << q for q in open_q)
+    out = []
+    for x in np.asarray(xs, dtype=np.uint64):
+        for j in range(1 << len(open_q)):
+            y = int(x) & ~mask
+            for i, q in enumerate(open_q):
+                y |= ((j >> i) & 1) << q
+            out.append(y)
+    return np.array(out, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT)])
+@pytest.mark.parametrize("open_q,js", [((0,), 0), ((2, 5, 7), 1), ((1, 3, 4, 8), 3)])
+def test_open_output_qubits_against_statevector(precision, tol, open_q, js):
+    # m open qubits: each bitstring yields the 2^m amplitudes of all values of those qubits
+    circ = random_grid_circuit(3, 3, 8, 71)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=72)
+    sl = tree_trimming(net, tree, 3, seed=72)
+    xs = random_bitstrings(9, 16, 73)
+    m = len(open_q)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), precision=precision, open_qubits=open_q,
+                     slice_batch_log2=js)
+    assert plan.info()["n_open"] == m
+    x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
+    amp = torch.zeros((len(xs), 1 << m, 2), dtype=torch.float64, device="cuda")
+    plan.contract(x, amp, (0, 3))
+    plan.contract(x, amp, (3, 8))  # disjoint slice ranges add (Eq. 2)
+    torch.cuda.synchronize()
+    h = amp.cpu().numpy()
+    got = (h[..., 0] + 1j * h[..., 1]).reshape(-1)
+    want = oracle.amplitudes_statevector(circ, _with_open_bits(xs, open_q))
+    assert rms_err(got, want) < tol
+    with pytest.raises(ValueError):
+        plan.contract(x, torch.zeros((len(xs), 2), dtype=torch.float64, device="cuda") if m else amp[:1])
+
+
+def test_all_qubits_open_gives_the_state():
+    circ = random_grid_circuit(2, 3, 6, 74)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=75)
+    plan = qxtn.Plan(net, tree, [], max_bitstrings=1, open_qubits=range(6))
+    amp = torch.zeros((1, 64, 2), dtype=torch.float64, device="cuda")
+    plan.contract(torch.zeros(1, dtype=torch.int64, device="cuda"), amp)
+    torch.cuda.synchronize()
+    h = amp.cpu().numpy()[0]
+    want = oracle.amplitudes_statevector(circ, np.arange(64, dtype=np.uint64))
+    assert rms_err(h[:, 0] + 1j * h[:, 1], want) < TOL_C64
+    assert abs(np.sum(np.abs(want) ** 2) - 1.0) < 1e-12

@@ -296,20 +296,23 @@ def summarize_trace(db_path, log_path):
         t[0] += 1
         t[1] += dur * 1e-6
     total = sum(v[1] for v in top.values())
-    # per kernel family, launches inside timed contract calls (the first call of each plan is the warm-up)
-    fam, calls, inside = {}, 0, False
+    # per kernel family, launches of the timed contract calls: a call is every dispatch after the previous
+    # call's k_block_finish up to its own (per-call products included, as in bench.py's events); the first
+    # call of each plan is the warm-up, which also holds that plan's autotuning trials
+    fam, calls, cur = {}, 0, []
     for name, dur in rows:
-        if "k_block_init" in name:
-            calls += 1
-            inside = calls % 4 != 1
-        elif "k_block_finish" in name:
-            inside = False
-        elif inside:
-            for short in KERNEL_NAMES.values():
-                if f"qx::{short}<" in name:
-                    f = fam.setdefault(short, [0, 0.0])
-                    f[0] += 1
-                    f[1] += dur * 1e-6
+        if "k_block_finish" not in name:
+            cur.append((name, dur))
+            continue
+        calls += 1
+        if calls % 4 != 1:
+            for n, d in cur:
+                for short in KERNEL_NAMES.values():
+                    if f"qx::{short}<" in n:
+                        f = fam.setdefault(short, [0, 0.0])
+                        f[0] += 1
+                        f[1] += d * 1e-6
+        cur = []
     line = None
     for l in open(log_path):
         if l.startswith("{"):

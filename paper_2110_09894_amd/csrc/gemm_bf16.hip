@@ -49,17 +49,13 @@ __device__ __forceinline__ int64_t k_offset(const OperandView& v, int k) {
 // a piece fills slot l & 7 of row l >> 3.  Element offsets of chunk starts are
 // multiples of 8 (k bits 0..2 are the three lowest strides), so a chunk's
 // plane q is the 16 bytes at BF16 offset 4 e0 + 8 q.
-#ifndef QX_BF16_VIA_REGS
-#define QX_BF16_VIA_REGS 0
-#endif
 template <int ROWS, int NW>
 struct DmaTile {
   static constexpr int NP = ROWS / 8;
-  static constexpr int NI = QX_BF16_VIA_REGS ? 0 : NP / NW;  // direct copies per wave
-  static constexpr int NJ = NP / NW;                          // pieces per wave
+  static constexpr int NJ = NP / NW;  // pieces per wave
+  static constexpr int NI = NJ;       // direct copies per wave per k tile
   static_assert(NJ * NW == NP, "pieces must divide evenly among the waves");
   int64_t goff[NJ];  // BF16 offset of this lane's 16 bytes, relative to the k tile origin
-  u32x4 reg[QX_BF16_VIA_REGS ? NJ : 1];
   __device__ inline void init(const OperandView& v, int64_t r0, int wave, int lane) {
     const int64_t k8 = k_offset(v, 8), base = origin_offset(v, r0);
 #pragma unroll
@@ -76,22 +72,14 @@ struct DmaTile {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const uint16_t* src = X + 4 * kb + goff[j];
-      if (QX_BF16_VIA_REGS) {
-        reg[j] = *(const u32x4*)src;
-      } else {
-        // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
+      // (device pass only: the host pass of a kernel that names this builtin would drop its launch stub)
 #if defined(__HIP_DEVICE_COMPILE__)
-        __builtin_amdgcn_global_load_lds(src, (lds_void*)(region + (wave + NW * j) * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(src, (lds_void*)(region + (wave + NW * j) * 1024), 16, 0, 0);
 #endif
-      }
     }
   }
-  __device__ inline void store(char* region, int wave, int lane) const {
-    if (QX_BF16_VIA_REGS) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) *(u32x4*)(region + (wave + NW * j) * 1024 + lane * 16) = reg[j];
-    }
-  }
+  // the copies land in LDS by themselves
+  __device__ inline void store(char*, int, int) const {}
 };
 
 // Register-staged copy for an operand that is not k-contiguous: consecutive
@@ -412,9 +400,6 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-#ifndef QX_BF16_NS128
-#define QX_BF16_NS128 2
-#endif
 
 hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
   // operands must be stored split, and K a multiple of the 16-wide k tile (or 8: one half tile)
@@ -425,7 +410,7 @@ hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
     case GEMM_TILE_64x128: return launch_bf16s<64, 128, 2, 2, 3>(a, s);
     case GEMM_TILE_256x128: return launch_bf16s<256, 128, 4, 2, 3>(a, s);
     case GEMM_TILE_128x256: return launch_bf16s<128, 256, 2, 4, 3>(a, s);
-    default: return launch_bf16s<128, 128, 2, 2, QX_BF16_NS128>(a, s);
+    default: return launch_bf16s<128, 128, 2, 2, 2>(a, s);
   }
 }
 

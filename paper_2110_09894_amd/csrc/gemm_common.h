@@ -173,9 +173,7 @@ __device__ inline OutMap out_map(const GemmArgs& p, int64_t m0, int64_t n0) {
 // product the tiles run in groups of QX_TILE_GROUP tile rows, m fastest, so the
 // work-groups resident on one XCD at a time cover a square-ish patch of C and
 // read few A and B panels, each shared by several of them through the L2.
-#ifndef QX_TILE_GROUP
-#define QX_TILE_GROUP 8
-#endif
+constexpr uint32_t QX_TILE_GROUP = 8;
 struct TileCoord {
   int item;
   int64_t tm, tn, aoff, boff, coff;
@@ -190,9 +188,9 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
   const uint32_t per = nwg / 8;
   if (per > 0 && w < per * 8) w = (w % 8) * per + w / 8;
   const uint32_t z = w / tiles, t = w % tiles;
-  const uint32_t group = (uint32_t)QX_TILE_GROUP * tiles_n;
-  const uint32_t g = t / group, first = g * (uint32_t)QX_TILE_GROUP, r = t - g * group;
-  const uint32_t gsz = tiles_m - first < (uint32_t)QX_TILE_GROUP ? tiles_m - first : (uint32_t)QX_TILE_GROUP;
+  const uint32_t group = QX_TILE_GROUP * tiles_n;
+  const uint32_t g = t / group, first = g * QX_TILE_GROUP, r = t - g * group;
+  const uint32_t gsz = tiles_m - first < QX_TILE_GROUP ? tiles_m - first : QX_TILE_GROUP;
   TileCoord tc;
   tc.tm = first + r % gsz;
   tc.tn = r / gsz;

@@ -169,13 +169,16 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
   }
 }
 
-// Shorter inner products (K <= 16384): one wavefront per output, four outputs
-// per work-group, reduced with cross-lane shuffles only (no LDS, no barrier).
-// A lane keeps four partial sums of at most K / 256 terms each.
+// Shorter inner products (K <= 16384): a group of L lanes per output (L = 16,
+// 32 or 64 for K >= 256, 512, 1024, so a lane sums at least 16 terms), 256 / L
+// outputs per work-group, reduced with cross-lane shuffles inside the group
+// only (no LDS, no barrier).  A lane keeps four partial sums of at most
+// K / (4 L) terms each.
+template <int L>
 __global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
-  const int lane = threadIdx.x & 63;
-  const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (o >= ((int64_t)1 << p.n_out)) return;  // whole waves only; nothing below waits for others
+  const int sub = threadIdx.x & (L - 1);
+  const int64_t o = (int64_t)blockIdx.x * (256 / L) + (threadIdx.x / L);
+  if (o >= ((int64_t)1 << p.n_out)) return;  // whole lane groups only; shuffles stay inside a group
   const int item = blockIdx.y;
   int64_t ao = (int64_t)item * p.a_item + (p.a_gather ? p.a_gather[item] : 0);
   int64_t bo = (int64_t)item * p.b_item + (p.b_gather ? p.b_gather[item] : 0);
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
   QxCplx acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f}, acc2 = {0.f, 0.f}, acc3 = {0.f, 0.f};
   const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (p.K & 3) == 0;
   if (vec) {
-    for (int64_t k = 4 * (int64_t)lane; k < p.K; k += 256) {
+    for (int64_t k = 4 * (int64_t)sub; k < p.K; k += 4 * L) {
       const v4f a0 = *(const v4f*)(A + k), a1 = *(const v4f*)(A + k + 2);
       const v4f b0 = *(const v4f*)(B + k), b1 = *(const v4f*)(B + k + 2);
       acc0 = cmul_acc(acc0, QxCplx{a0[0], a0[1]}, QxCplx{b0[0], b0[1]});
@@ -196,15 +199,15 @@ __global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
       acc3 = cmul_acc(acc3, QxCplx{a1[2], a1[3]}, QxCplx{b1[2], b1[3]});
     }
   } else {
-    for (int64_t k = lane; k < p.K; k += 64) acc0 = cmul_acc(acc0, A[k], B[k]);
+    for (int64_t k = sub; k < p.K; k += L) acc0 = cmul_acc(acc0, A[k], B[k]);
   }
   QxCplx acc = {(acc0.x + acc1.x) + (acc2.x + acc3.x), (acc0.y + acc1.y) + (acc2.y + acc3.y)};
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+  for (int off = L / 2; off >= 1; off >>= 1) {
     acc.x += __shfl_xor(acc.x, off, 64);
     acc.y += __shfl_xor(acc.y, off, 64);
   }
-  if (lane == 0) {
+  if (sub == 0) {
     if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc);
     else p.c[(int64_t)item * p.c_item + o] = acc;
   }
@@ -411,8 +414,14 @@ int gemm_default_tile(int64_t M, int64_t N) {
 
 hipError_t launch_dot(const DotArgs& a, hipStream_t s) {
   if (a.K <= 16384) {
-    dim3 grid((unsigned)(((1LL << a.n_out) + 3) / 4), (unsigned)a.n_items);
-    hipLaunchKernelGGL(k_dot_wave, grid, dim3(256), 0, s, a);
+    const int64_t n = 1LL << a.n_out;
+    if (a.K >= 1024) {
+      hipLaunchKernelGGL(k_dot_wave<64>, dim3((unsigned)((n + 3) / 4), (unsigned)a.n_items), dim3(256), 0, s, a);
+    } else if (a.K >= 512) {
+      hipLaunchKernelGGL(k_dot_wave<32>, dim3((unsigned)((n + 7) / 8), (unsigned)a.n_items), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(k_dot_wave<16>, dim3((unsigned)((n + 15) / 16), (unsigned)a.n_items), dim3(256), 0, s, a);
+    }
   } else {
     dim3 grid((unsigned)(1LL << a.n_out), (unsigned)a.n_items);
     hipLaunchKernelGGL(k_dot, grid, dim3(256), 0, s, a);

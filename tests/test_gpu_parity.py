@@ -332,3 +332,29 @@ def test_all_qubits_open_gives_the_state():
     want = oracle.amplitudes_statevector(circ, np.arange(64, dtype=np.uint64))
     assert rms_err(h[:, 0] + 1j * h[:, 1], want) < TOL_C64
     assert abs(np.sum(np.abs(want) ** 2) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("bits", [8, 9, 10, 14, 15])
+@pytest.mark.parametrize("open_q", [(), (0, 1)])
+def test_long_inner_products(bits, open_q):
+    # two dense leaves sharing `bits` summed labels, one output wire each: the root is an inner product of
+    # K = 2^bits terms (lane groups of 16 / 32 / 64 up to 2^14, a work-group per output above)
+    from workloads import Network
+    rng = np.random.default_rng(100 + bits)
+    shape = (2,) * (bits + 1)
+    t1 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    t2 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ks = tuple(range(bits))
+    net = Network([t1, t2], [ks + (100,), ks + (101,)], [100, 101], 2)
+    tree = np.array([[0, 1]], dtype=np.int32)
+    xs = np.arange(4, dtype=np.uint64)
+    plan = qxtn.Plan(net, tree, [], max_bitstrings=4, open_qubits=open_q)
+    m = len(open_q)
+    x = torch.from_numpy(xs.view(np.int64)).cuda()
+    amp = torch.zeros((4, 1 << m, 2), dtype=torch.float64, device="cuda")
+    plan.contract(x, amp)
+    torch.cuda.synchronize()
+    h = amp.cpu().numpy()
+    got = (h[..., 0] + 1j * h[..., 1]).reshape(-1)
+    want = np.array([oracle.contract_slice(net, tree, int(y)) for y in _with_open_bits(xs, open_q)])
+    assert rms_err(got, want) < TOL_C64

@@ -238,6 +238,29 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def permute_measure(rank=26, reps=10):
+    """k_permute alone on a 2^rank-element random bit permutation (seed 7): HBM roofline, 16 bytes per
+    element (one read, one write), average over ``reps`` launches timed with events on the current stream."""
+    import torch
+    from paper_2110_09894_amd import qxtn
+    rng = np.random.default_rng(7)
+    in_pos = rng.permutation(rank).astype(np.int32)
+    src = torch.randn(2 << rank, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    qxtn.permute_c64(src, dst, in_pos, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        qxtn.permute_c64(src, dst, in_pos, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    gbs = 16.0 * (1 << rank) / sec / 1e9
+    return {"kernel": "k_permute", "elements": 1 << rank, "avg_launch_ms": sec * 1e3, "achieved_gbs": gbs,
+            "frac_of_hbm_peak": gbs * 1e9 / HBM_PEAK, "in_pos_seed": 7}
+
+
 def refined_note(args):
     cost = f"roofline cost, {args.mem_weight:g} flops per element moved" if args.mem_weight else "flop cost"
     note = (f"; tree refined by local sub-tree re-ordering ({cost}) of the best {args.reconfigure} greedy trials"
@@ -375,6 +398,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--permute-only", action="store_true", help="time only k_permute (2^26 elements)")
     ap.add_argument("--summarize-traffic", metavar="DIR", help="write the HBM traffic summary from counter runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "LOG"), help="write the kernel-time summary")
     args = ap.parse_args()
@@ -386,6 +410,11 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.permute_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"permute": permute_measure(reps=args.steps * 10)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -502,26 +531,7 @@ def main():
 
     # index-permute primitive on its own (the workload's plan needs none): HBM roofline
     if not args.no_permute:
-        rank = 26
-        rng = np.random.default_rng(7)
-        in_pos = rng.permutation(rank).astype(np.int32)
-        src = torch.randn(2 << rank, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        qxtn.permute_c64(src, dst, in_pos, 1)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 10
-        e0.record()
-        for _ in range(reps):
-            qxtn.permute_c64(src, dst, in_pos, 1)
-        e1.record()
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / reps
-        gbs = 16.0 * (1 << rank) / sec / 1e9
-        out["permute"] = {"kernel": "k_permute", "elements": 1 << rank, "avg_launch_ms": sec * 1e3,
-                          "achieved_gbs": gbs, "frac_of_hbm_peak": gbs * 1e9 / HBM_PEAK,
-                          "in_pos_seed": 7}
-        del src, dst
+        out["permute"] = permute_measure()
 
     # accuracy on slice 0 and the CPU baseline share the oracle sample
     if not args.no_cpu_baseline:

@@ -17,6 +17,7 @@
 #define QX_MAX_HBITS 16     // shared slice bits of one matrix product (batch)
 #define QX_MAX_SBITS 24     // slice bits carried to the root
 #define QX_MAX_OBITS 16     // open output qubits (amplitudes per bitstring = 2^m)
+#define QX_PERM_TB 6        // a permute tile: the output's 6 lowest bits and the input's 6 lowest positions
 
 struct QxCplx { float x, y; };
 
@@ -95,7 +96,7 @@ struct DotArgs {
 
 // Bit permutation: out[item][o] = in[item][sum_i bit_i(o) << in_pos[i]]
 // The host splits the bits into a tile (the output's lowest bits plus the bits
-// at the input's lowest positions, at most 10) and outer bits.
+// at the input's lowest positions, at most 2 QX_PERM_TB) and outer bits.
 struct PermArgs {
   const QxCplx *in;
   QxCplx *out;
@@ -103,9 +104,10 @@ struct PermArgs {
   int32_t rank, n_items;
   int32_t in_pos[QX_MAX_BITS];
   int32_t nt, n_outer;                  // tile bits, outer bits
-  int32_t tl[10];                       // tile bits (output-bit indices), ascending
-  int32_t ll[10];                       // tile-bit slots in ascending input position
+  int32_t tl[2 * QX_PERM_TB];           // tile bits (output-bit indices), ascending
+  int32_t ll[2 * QX_PERM_TB];           // tile-bit slots in ascending input position
   int64_t outer_in[QX_MAX_BITS], outer_out[QX_MAX_BITS];  // strides of outer bit i
+  int32_t vec, pad_;                    // 16-byte pair accesses (aligned pointers, even item strides)
 };
 
 // Sum over the slices of one block, FP64, ascending slice order:

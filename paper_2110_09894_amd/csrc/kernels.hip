@@ -232,40 +232,105 @@ __global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
 // the output, transposing through LDS.  The outer bits select the tile.  Each
 // work-group builds its offset tables once and then walks many tiles.
 // ---------------------------------------------------------------------------
-constexpr int PERM_TB = 5;
+constexpr int PERM_TB = QX_PERM_TB;
+constexpr int PERM_TSZ = 1 << (2 * PERM_TB);     // largest tile (elements)
+constexpr int PERM_PAIRS = PERM_TSZ / 2 / 256;   // element pairs per thread per tile
+constexpr int PERM_HALF = 1 << PERM_TB;          // entries of each half-table
 __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
-  __shared__ QxCplx buf[1 << (2 * PERM_TB)];
-  __shared__ long long tin[1 << (2 * PERM_TB)];   // load order v -> input offset inside tile
-  __shared__ short tlu[1 << (2 * PERM_TB)];       // load order v -> LDS slot
-  __shared__ long long tout[1 << (2 * PERM_TB)];  // LDS slot u -> output offset inside tile
+  __shared__ QxCplx buf[PERM_TSZ];
+  // offsets split into the low and high PERM_TB bits of the load order v / LDS slot u:
+  // in(v) = tin[0][v & 63] + tin[1][v >> 6], slot(v) = tlu[0][..] | tlu[1][..], out(u) likewise
+  __shared__ long long tin[2][PERM_HALF], tout[2][PERM_HALF];
+  __shared__ int tlu[2][PERM_HALF];
   const int nt = p.nt;
   const int tsz = 1 << nt;
-  for (int v = threadIdx.x; v < tsz; v += blockDim.x) {
+  for (int x = threadIdx.x; x < 2 * PERM_HALF; x += blockDim.x) {
+    const int h = x / PERM_HALF, e = x % PERM_HALF;
     long long inoff = 0, outoff = 0;
     int u = 0;
-    for (int b = 0; b < nt; ++b)
-      if ((v >> b) & 1) {
+    for (int c = 0; c < PERM_TB; ++c) {
+      const int b = h * PERM_TB + c;
+      if (b < nt && ((e >> c) & 1)) {
         inoff += 1LL << p.in_pos[p.tl[p.ll[b]]];
         u |= 1 << p.ll[b];
         outoff += 1LL << p.tl[b];
       }
-    tin[v] = inoff;
-    tlu[v] = (short)u;
-    tout[v] = outoff;
+    }
+    tin[h][e] = inoff;
+    tlu[h][e] = u;
+    tout[h][e] = outoff;
   }
+  auto in_off = [&](int v) { return tin[0][v & (PERM_HALF - 1)] + tin[1][v >> PERM_TB]; };
+  auto slot = [&](int v) { return tlu[0][v & (PERM_HALF - 1)] | tlu[1][v >> PERM_TB]; };
+  auto out_off = [&](int u) { return tout[0][u & (PERM_HALF - 1)] + tout[1][u >> PERM_TB]; };
   const int64_t n_tiles = (int64_t)1 << p.n_outer;
   const int64_t total = n_tiles * p.n_items;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  auto bases = [&](int64_t t, int64_t& ib, int64_t& ob) {
     const int64_t item = t >> p.n_outer;
-    int64_t w = t & (n_tiles - 1), ibase = item * p.in_item, obase = item * p.out_item;
+    int64_t w = t & (n_tiles - 1);
+    ib = item * p.in_item;
+    ob = item * p.out_item;
     for (int i = 0; w; ++i, w >>= 1)
-      if (w & 1) { ibase += p.outer_in[i]; obase += p.outer_out[i]; }
-    __syncthreads();  // tables ready / previous tile's LDS reads done
-    const QxCplx* __restrict__ in = p.in + ibase;
-    for (int v = threadIdx.x; v < tsz; v += blockDim.x) buf[tlu[v]] = in[tin[v]];
+      if (w & 1) { ib += p.outer_in[i]; ob += p.outer_out[i]; }
+  };
+  if (!p.vec) {
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+      int64_t ibase, obase;
+      bases(t, ibase, obase);
+      __syncthreads();  // tables ready / previous tile's LDS reads done
+      const QxCplx* __restrict__ in = p.in + ibase;
+      for (int v = threadIdx.x; v < tsz; v += blockDim.x) buf[slot(v)] = in[in_off(v)];
+      __syncthreads();
+      QxCplx* __restrict__ out = p.out + obase;
+      for (int u = threadIdx.x; u < tsz; u += blockDim.x) out[out_off(u)] = buf[u];
+    }
+    return;
+  }
+  // Pairs: load-order bit 0 is input bit 0 and LDS slot bit 0 is output bit 0, so elements 2i and
+  // 2i + 1 are adjacent in the input (load order) and in the output (slot order): 16-byte accesses.
+  // The next tile's loads are issued before the current tile is written out.
+  const int npair = tsz >> 1;
+  __syncthreads();  // tables ready
+  int64_t t = blockIdx.x;
+  if (t >= total) return;  // uniform over the work-group
+  int64_t ibase, obase;
+  bases(t, ibase, obase);
+  v4f cur[PERM_PAIRS];
+#pragma unroll
+  for (int r = 0; r < PERM_PAIRS; ++r) {
+    const int i = threadIdx.x + 256 * r;
+    if (i < npair) cur[r] = *(const v4f*)(p.in + ibase + in_off(2 * i));
+  }
+  for (; t < total; t += gridDim.x) {
+#pragma unroll
+    for (int r = 0; r < PERM_PAIRS; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if (i < npair) {
+        buf[slot(2 * i)] = QxCplx{cur[r][0], cur[r][1]};
+        buf[slot(2 * i + 1)] = QxCplx{cur[r][2], cur[r][3]};
+      }
+    }
     __syncthreads();
-    QxCplx* __restrict__ out = p.out + obase;
-    for (int u = threadIdx.x; u < tsz; u += blockDim.x) out[tout[u]] = buf[u];
+    const int64_t tn = t + gridDim.x;
+    int64_t ib2 = 0, ob2 = obase;
+    if (tn < total) {
+      bases(tn, ib2, ob2);
+#pragma unroll
+      for (int r = 0; r < PERM_PAIRS; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        if (i < npair) cur[r] = *(const v4f*)(p.in + ib2 + in_off(2 * i));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PERM_PAIRS; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if (i < npair) {
+        const QxCplx a = buf[2 * i], b = buf[2 * i + 1];
+        *(v4f*)(p.out + obase + out_off(2 * i)) = v4f{a.x, a.y, b.x, b.y};
+      }
+    }
+    __syncthreads();  // LDS reads done before the next tile is written
+    obase = ob2;
   }
 }
 
@@ -450,10 +515,15 @@ void permute_setup(PermArgs& a) {
   a.n_outer = no;
 }
 
-hipError_t launch_permute(const PermArgs& a, hipStream_t s) {
+hipError_t launch_permute(const PermArgs& a_in, hipStream_t s) {
+  PermArgs a = a_in;
   const int64_t total = ((int64_t)1 << a.n_outer) * a.n_items;
   const int64_t grid = total < 4096 ? total : 4096;
   if (grid <= 0) return hipSuccess;
+  // pair accesses need 16-byte aligned tile bases: aligned pointers and even item strides (outer
+  // strides are at least 2^PERM_TB elements); a one-element tile has no pairs
+  a.vec = a.nt >= 1 && ((((uintptr_t)a.in) | ((uintptr_t)a.out)) & 15) == 0 && (a.in_item & 1) == 0 &&
+          (a.out_item & 1) == 0;
   hipLaunchKernelGGL(k_permute, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -14,6 +14,9 @@
 * Each bitstring's amplitude is computed independently of the others in its
   call, with the same plan inputs and kernels, so a request's result is the same
   alone and in a mix.
+* A circuit registered with open output qubits answers every bitstring with the
+  2^m amplitudes of all values of those qubits (one contraction, Sec. II); its
+  results are [n, 2^m] arrays.
 * Sampling requests run the empirical-supremum rejection sampler (Sec. III-B):
   each batch of candidates is one amplitude work item; accept / reject runs on
   the host when it completes and the next batch is queued.
@@ -46,7 +49,7 @@ def _bucket(b: int, cap: int) -> int:
 
 class _Circuit:
     def __init__(self, name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune,
-                 plan_budget):
+                 plan_budget, open_qubits=()):
         self.name = name
         self.network = network
         self.tree = tree
@@ -54,9 +57,12 @@ class _Circuit:
         self.precision = precision
         self.max_b = int(max_bitstrings)
         self.autotune = autotune
+        self.open_qubits = sorted(int(q) for q in open_qubits)
+        self.per = 1 << len(self.open_qubits)   # amplitudes per bitstring
         # the slice batch is resolved once (within the per-plan budget) so every replica is the same plan
         dry = qxtn.Plan(network, tree, self.sliced, precision=precision, max_bitstrings=self.max_b,
-                        slice_batch_log2=slice_batch_log2, dry_run=True, hbm_budget_bytes=plan_budget)
+                        slice_batch_log2=slice_batch_log2, dry_run=True, hbm_budget_bytes=plan_budget,
+                        open_qubits=self.open_qubits)
         self.js = dry.info()["slice_batch_log2"]
         self.device_bytes = dry.info()["device_bytes"]
         self.n_slices = 1 << len(self.sliced)
@@ -72,7 +78,7 @@ class _Replica:
         with torch.cuda.stream(self.stream):
             self.plan = qxtn.Plan(circ.network, circ.tree, circ.sliced, precision=circ.precision,
                                   max_bitstrings=circ.max_b, slice_batch_log2=circ.js,
-                                  autotune=circ.autotune, stream=self.stream)
+                                  autotune=circ.autotune, open_qubits=circ.open_qubits, stream=self.stream)
         self.device_bytes = self.plan.info()["device_bytes"]
         self.busy = None          # in-flight call, or None
         self.last_used = time.monotonic()
@@ -94,7 +100,7 @@ class _Request:
         self.sample = sample      # dict for sampling requests
         if bitstrings is not None:
             self.bitstrings = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
-            self.result = np.zeros(len(self.bitstrings), dtype=np.complex128)
+            self.result = None        # shaped by the circuit when enqueued
             self.remaining = len(self.bitstrings)
             self.next_off = 0
 
@@ -120,9 +126,9 @@ class Server:
 
     # ------------------------------------------------------------------ setup
     def register(self, name, network, tree, sliced=(), precision="c64", max_bitstrings=1024,
-                 slice_batch_log2=-1, autotune=False):
+                 slice_batch_log2=-1, autotune=False, open_qubits=()):
         circ = _Circuit(name, network, tree, sliced, precision, max_bitstrings, slice_batch_log2, autotune,
-                        self.plan_budget)
+                        self.plan_budget, open_qubits)
         if circ.device_bytes > self.budget:
             raise AdmissionError(f"plan for {name} needs {circ.device_bytes} bytes, budget {self.budget}")
         with self.lock:
@@ -169,6 +175,8 @@ class Server:
             self.rejected += 1
             req.future.set_exception(AdmissionError(f"unknown circuit {req.circuit}"))
             return
+        n = len(req.bitstrings)
+        req.result = np.zeros((n, circ.per) if circ.per > 1 else n, dtype=np.complex128)
         with self.lock:
             self.pending.append(req)
             self.lock.notify_all()
@@ -193,8 +201,14 @@ class Server:
     def _sample_step(self, sub):
         req = sub.parent
         s = req.sample
-        N = float(2.0 ** self.circuits[req.circuit].n_qubits)
-        for x, a in zip(sub.bitstrings, sub.result):
+        circ = self.circuits[req.circuit]
+        N = float(2.0 ** circ.n_qubits)
+        vals = sub.result
+        if circ.per > 1:
+            # the candidate's amplitude is the value whose open bits are its own
+            own = [sum(((int(x) >> q) & 1) << i for i, q in enumerate(circ.open_qubits)) for x in sub.bitstrings]
+            vals = sub.result[np.arange(len(own)), own]
+        for x, a in zip(sub.bitstrings, vals):
             if len(s["kept"]) >= s["n"]:
                 break
             i = s["used"]
@@ -242,9 +256,9 @@ class Server:
         with torch.cuda.stream(rep.stream):
             hx = torch.from_numpy(xs.view(np.int64)).pin_memory()
             dx = hx.to(f"cuda:{self.device}", non_blocking=True)
-            amp = torch.zeros((Bp, 2), dtype=torch.float64, device=f"cuda:{self.device}")
+            amp = torch.zeros((Bp, circ.per, 2), dtype=torch.float64, device=f"cuda:{self.device}")
             rep.plan.contract(dx, amp, (0, circ.n_slices), stream=rep.stream)
-            host = torch.empty((Bp, 2), dtype=torch.float64).pin_memory()
+            host = torch.empty((Bp, circ.per, 2), dtype=torch.float64).pin_memory()
             host.copy_(amp, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(rep.stream)
@@ -253,7 +267,9 @@ class Server:
     def _complete(self, rep):
         call = rep.busy
         h = call["host"].numpy()
-        vals = h[:, 0] + 1j * h[:, 1]
+        vals = h[..., 0] + 1j * h[..., 1]
+        if vals.shape[1] == 1:
+            vals = vals[:, 0]
         pos = 0
         now = time.monotonic()
         for req, o, c in call["parts"]:
@@ -265,7 +281,7 @@ class Server:
                     self._sample_step(req)
                 else:
                     self.latencies.append(now - req.arrival)
-                    self.completed_amplitudes += len(req.bitstrings)
+                    self.completed_amplitudes += req.result.size
                     req.future.set_result(req.result)
         rep.busy = None
         rep.last_used = now

@@ -111,3 +111,39 @@ def test_sampling_request_matches_direct_sampler_and_oracle():
     assert len(mismatch) <= 2, mismatch
     if len(mismatch) == 0:
         assert np.array_equal(samples, want)
+
+
+def _with_open_bits(xs, open_q):
+    mask = sum(1 << q for q in open_q)
+    out = []
+    for x in np.asarray(xs, dtype=np.uint64):
+        for j in range(1 << len(open_q)):
+            y = int(x) & ~mask
+            for i, q in enumerate(open_q):
+                y |= ((j >> i) & 1) << q
+            out.append(y)
+    return np.array(out, dtype=np.uint64)
+
+
+def test_open_output_circuit_in_the_mix():
+    # the same circuit registered closed and with qubits 1 and 3 open: requests of both kinds interleave;
+    # every open result is [n, 4] and matches the state vector, the closed ones are unchanged
+    circ, net, tree, sl = _circuits()["g16"]
+    srv = Server(max_replicas=2)
+    srv.register("closed", net, tree, sl, max_bitstrings=64)
+    srv.register("open13", net, tree, sl, max_bitstrings=64, open_qubits=(3, 1))
+    srv.start()
+    reqs = [("open13" if i % 2 else "closed", random_bitstrings(16, 5 + 7 * i, 200 + i)) for i in range(8)]
+    futs = [srv.submit_amplitudes(name, xs) for name, xs in reqs]
+    res = [f.result(timeout=120) for f in futs]
+    st = srv.stats()
+    srv.stop()
+    assert st["completed_amplitudes"] == sum(len(xs) * (4 if name == "open13" else 1) for name, xs in reqs)
+    for (name, xs), got in zip(reqs, res):
+        if name == "open13":
+            assert got.shape == (len(xs), 4)
+            want = oracle.amplitudes_statevector(circ, _with_open_bits(xs, (1, 3))).reshape(len(xs), 4)
+        else:
+            assert got.shape == (len(xs),)
+            want = oracle.amplitudes_statevector(circ, xs)
+        assert rms_err(got.reshape(-1), want.reshape(-1)) < 1e-5

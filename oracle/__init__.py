@@ -16,7 +16,8 @@ Three independent computations of one definition, all in complex128:
 * ``tree_contract`` (O3) -- pairwise contraction along a given tree
   (Sec. III-A) of each slice's network, slices summed (Eq. 2).
 * ``sampling`` -- empirical-supremum rejection sampling (Sec. III-B) from the
-  exact O1 probabilities.
+  exact O1 probabilities, per bitstring and per group of bitstrings that share
+  all but some open output qubits.
 
 Every function here is pinned by tests against closed forms, invariants and the
 other two computations; none is "parity unpinned".
@@ -24,8 +25,8 @@ other two computations; none is "parity unpinned".
 from .statevector import statevector, amplitudes_statevector
 from .bruteforce import amplitude_bruteforce
 from .tree_contract import contract_slice, amplitude_sliced, amplitudes_sliced, slice_values
-from .sampling import probabilities, empirical_supremum_sample
+from .sampling import probabilities, empirical_supremum_sample, empirical_supremum_sample_groups
 
 __all__ = ["statevector", "amplitudes_statevector", "amplitude_bruteforce", "contract_slice",
            "amplitude_sliced", "amplitudes_sliced", "slice_values", "probabilities",
-           "empirical_supremum_sample"]
+           "empirical_supremum_sample", "empirical_supremum_sample_groups"]

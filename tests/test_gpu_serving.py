@@ -147,3 +147,34 @@ def test_open_output_circuit_in_the_mix():
             assert got.shape == (len(xs),)
             want = oracle.amplitudes_statevector(circ, xs)
         assert rms_err(got.reshape(-1), want.reshape(-1)) < 1e-5
+
+
+def test_group_sampler_on_open_output_plan():
+    # the open-output plan gives each candidate's group of 2^m amplitudes in one contraction; the group
+    # sampler's decisions agree with the oracle's on exact probabilities except where the margin is below
+    # the amplitude error
+    from paper_2110_09894_amd.sampling import rejection_sample_groups
+    from workloads import group_sampling_inputs
+    circs = _circuits()
+    circ, net, tree, sl = circs["g12"]
+    open_q = (2, 6, 9)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=64, open_qubits=open_q)
+
+    def fn(cand):
+        x = torch.from_numpy(np.ascontiguousarray(cand).view(np.int64)).cuda()
+        amp = torch.zeros((len(cand), 8, 2), dtype=torch.float64, device="cuda")
+        plan.contract(x, amp)
+        torch.cuda.synchronize()
+        h = amp.cpu().numpy()
+        return h[..., 0] + 1j * h[..., 1]
+
+    cand, u, c = group_sampling_inputs(12, 2000, 31)
+    got, info = rejection_sample_groups(fn, 12, open_q, cand, u, c, 200, warmup=32, batch=64)
+    want, dec = oracle.empirical_supremum_sample_groups(oracle.probabilities(circ), 12, open_q, cand, u, c, 200,
+                                                        warmup=32)
+    n = min(len(dec), len(info["decisions"]))
+    mismatch = np.nonzero(info["decisions"][:n] != dec[:n])[0]
+    assert len(mismatch) <= 2, mismatch
+    if len(mismatch) == 0:
+        assert np.array_equal(got, want)
+    assert len(got) == 200

@@ -11,3 +11,11 @@ def sampling_inputs(n_qubits: int, count: int, seed: int):
     cand = random_bitstrings(n_qubits, count, seed)
     u = np.random.Generator(np.random.PCG64(seed + 7919)).random(count)
     return cand, u
+
+
+def group_sampling_inputs(n_qubits: int, count: int, seed: int):
+    """Inputs of the open-output (group) sampler: candidates, an acceptance uniform per candidate and a
+    second uniform per candidate that picks the member of an accepted group."""
+    cand, u = sampling_inputs(n_qubits, count, seed)
+    c = np.random.Generator(np.random.PCG64(seed + 104729)).random(count)
+    return cand, u, c

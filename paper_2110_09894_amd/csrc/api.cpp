@@ -291,9 +291,9 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
       int bm, bn;
       gemm_tile_dims(t, bm, bn);
       if (bm > std::max<int64_t>(64, g.M) || bn > std::max<int64_t>(64, g.N)) continue;
-      // the first launch is a warm-up; the best of up to 5 more counts (fewer for long products)
+      // the first launch is a warm-up; the best of 2 to 5 more counts (2 for long products)
       float ms_min = 1e30f, spent = 0.f;
-      for (int rep = 0; rep < 6 && !(rep >= 2 && spent > 40.f); ++rep) {
+      for (int rep = 0; rep < 6 && !(rep >= 3 && spent > 40.f); ++rep) {
         HIP_TRY(hipEventRecord(e0, s));
         HIP_TRY(launch_gemm(g, p->pc.precision, t, s));
         HIP_TRY(hipEventRecord(e1, s));

@@ -285,28 +285,43 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
         continue;
       }
     }
-    int best = op.tile;
-    float best_ms = 1e30f;
+    // candidate shapes: one untimed warm-up each, then rounds that time every candidate once, in turn,
+    // so clock drift affects them alike; at least 2 rounds, up to 5 while a round stays short.  Keep the
+    // shape with the smallest time.
+    std::vector<int> cand;
     for (int t = 0; t < GEMM_N_TILES; ++t) {
       int bm, bn;
       gemm_tile_dims(t, bm, bn);
-      if (bm > std::max<int64_t>(64, g.M) || bn > std::max<int64_t>(64, g.N)) continue;
-      // the first launch is a warm-up; the best of 2 to 5 more counts (2 for long products)
-      float ms_min = 1e30f, spent = 0.f;
-      for (int rep = 0; rep < 6 && !(rep >= 3 && spent > 40.f); ++rep) {
+      if (bm <= std::max<int64_t>(64, g.M) && bn <= std::max<int64_t>(64, g.N)) cand.push_back(t);
+    }
+    int best = op.tile;
+    if (!cand.empty()) {
+      std::vector<float> ms_min(cand.size(), 1e30f);
+      float round_ms = 0.f;
+      for (size_t c = 0; c < cand.size(); ++c) {
         HIP_TRY(hipEventRecord(e0, s));
-        HIP_TRY(launch_gemm(g, p->pc.precision, t, s));
+        HIP_TRY(launch_gemm(g, p->pc.precision, cand[c], s));
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        spent += ms;
-        if (rep > 0) ms_min = std::min(ms_min, ms);
+        round_ms += ms;
       }
-      if (ms_min < best_ms) {
-        best_ms = ms_min;
-        best = t;
-      }
+      const int rounds = std::max(2, std::min(5, (int)(200.f / std::max(round_ms, 1e-3f))));
+      for (int r = 0; r < rounds; ++r)
+        for (size_t c = 0; c < cand.size(); ++c) {
+          HIP_TRY(hipEventRecord(e0, s));
+          HIP_TRY(launch_gemm(g, p->pc.precision, cand[c], s));
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+          ms_min[c] = std::min(ms_min[c], ms);
+        }
+      size_t bi = 0;
+      for (size_t c = 1; c < cand.size(); ++c)
+        if (ms_min[c] < ms_min[bi]) bi = c;
+      best = cand[bi];
     }
     op.tile = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -114,3 +114,18 @@ def test_roofline_cost_and_refinement():
     xs = random_bitstrings(12, 6, 5)
     got = oracle.amplitudes_sliced(net, new, xs, sliced)
     assert np.max(np.abs(got - oracle.amplitudes_statevector(circ, xs))) < 1e-14
+
+
+def test_refined_c2_tree_compiles_and_is_cheaper():
+    # the 30-qubit configuration's refined tree (bench.py --reconfigure 4) compiles into a plan and does far
+    # less work per slice than the greedy tree the configuration uses
+    from paper_2110_09894_amd import qxtn
+    from workloads import configs
+    w = configs.get("c2")
+    tree0, sl0, st0 = w.plan_inputs()
+    tree, sl, st = w.plan_inputs(reconfigure=4, mem_weight=16.0)
+    assert st["width"] <= st0["width"] and st["total_flops"] < st0["total_flops"] / 4
+    p0 = qxtn.Plan(w.network(), tree0, sl0, max_bitstrings=256, slice_batch_log2=4, dry_run=True).info()
+    p1 = qxtn.Plan(w.network(), tree, sl, max_bitstrings=256, slice_batch_log2=4, dry_run=True).info()
+    assert p1["flops_per_slice"] < p0["flops_per_slice"] / 4
+    assert p1["width"] == st["width"]

@@ -153,25 +153,42 @@ def summarize_traffic(run_dir):
     print(TRAFFIC_FILE)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, tree, sliced, xs, seconds):
-    """Oracle (complex128 tensordot) on slice 0 for as many bitstrings as fit in ``seconds``."""
+    """Oracle (complex128 tensordot) on slice 0 for as many bitstrings as fit in ``seconds`` with the host BLAS's
+    own thread count, then a shorter sample with one BLAS thread."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        info = threadpool_info()
+        blas_threads = max([d.get("num_threads", 1) for d in info] or [1])
+        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in info) or None
     except Exception:
-        blas_threads = None
+        threadpool_limits, blas_threads, blas = None, None, None
     net = w.network()
-    vals = []
-    t0 = time.perf_counter()
-    while True:
-        vals.append(oracle.contract_slice(net, tree, xs[len(vals)], sliced, 0))
-        el = time.perf_counter() - t0
-        if el >= seconds or len(vals) == len(xs):
-            break
-    per = el / len(vals)
     n_slices = 1 << len(sliced)
-    return {
+
+    def sample(budget, limit):
+        vals = []
+        t0 = time.perf_counter()
+        while True:
+            vals.append(oracle.contract_slice(net, tree, xs[len(vals)], sliced, 0))
+            el = time.perf_counter() - t0
+            if el >= budget or len(vals) == len(xs) or len(vals) >= limit:
+                return vals, el
+
+    vals, el = sample(seconds, len(xs))
+    per = el / len(vals)
+    out = {
         "value": 1.0 / (per * n_slices),
         "unit": "amplitudes/s",
         "cores": blas_threads or len(os.sched_getaffinity(0)),
@@ -179,7 +196,16 @@ def cpu_baseline(w, tree, sliced, xs, seconds):
         "sample": f"FP64 oracle (numpy complex128 pairwise tensordot along the same tree) on slice 0 for "
                   f"{len(vals)} bitstrings in {el:.1f} s, extrapolated x{n_slices} slices",
         "host_cpus": len(os.sched_getaffinity(0)),
-    }, np.array(vals)
+        "cpu_model": cpu_model(),
+        "blas": blas,
+    }
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v1, el1 = sample(seconds / 3, len(xs))
+        out["single_thread"] = {"value": 1.0 / (el1 / len(v1) * n_slices), "unit": "amplitudes/s", "cores": 1,
+                                "sample": f"slice 0, {len(v1)} bitstrings in {el1:.1f} s, extrapolated "
+                                          f"x{n_slices} slices"}
+    return out, np.array(vals)
 
 
 def serve_bench(args):

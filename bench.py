@@ -164,47 +164,56 @@ def cpu_model():
 
 
 def cpu_baseline(w, tree, sliced, xs, seconds):
-    """Oracle (complex128 tensordot) on slice 0 for as many bitstrings as fit in ``seconds`` with the host BLAS's
-    own thread count, then a shorter sample with one BLAS thread."""
+    """Oracle (complex128 tensordot) on as many (slice, bitstring) pairs as fit in ``seconds`` with the host
+    BLAS's own thread count, then a third as long with one BLAS thread."""
     import oracle
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
         info = threadpool_info()
         blas_threads = max([d.get("num_threads", 1) for d in info] or [1])
-        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in info) or None
+        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in info
+                         if d.get("user_api") == "blas") or None
     except Exception:
         threadpool_limits, blas_threads, blas = None, None, None
     net = w.network()
     n_slices = 1 << len(sliced)
 
-    def sample(budget, limit):
-        vals = []
+    def sample(budget):
+        """Slice-amplitudes (slice s, bitstring b), slice-major from slice 0, until ``budget`` seconds pass
+        (at least one slice-amplitude); returns slice 0's values, the pairs done and the elapsed time."""
+        vals, done = [], 0
         t0 = time.perf_counter()
-        while True:
-            vals.append(oracle.contract_slice(net, tree, xs[len(vals)], sliced, 0))
-            el = time.perf_counter() - t0
-            if el >= budget or len(vals) == len(xs) or len(vals) >= limit:
-                return vals, el
+        for s in range(n_slices):
+            for b in range(len(xs)):
+                v = oracle.contract_slice(net, tree, xs[b], sliced, s)
+                if s == 0:
+                    vals.append(v)
+                done += 1
+                el = time.perf_counter() - t0
+                if el >= budget:
+                    return vals, done, el
+        return vals, done, time.perf_counter() - t0
 
-    vals, el = sample(seconds, len(xs))
-    per = el / len(vals)
+    def describe(done, el):
+        return (f"{done} slice-amplitudes (slices from 0 upward x {len(xs)} bitstrings) in {el:.1f} s, "
+                f"scaled to {n_slices} slices per amplitude")
+
+    vals, done, el = sample(seconds)
     out = {
-        "value": 1.0 / (per * n_slices),
+        "value": done / el / n_slices,
         "unit": "amplitudes/s",
         "cores": blas_threads or len(os.sched_getaffinity(0)),
         "kind": "oracle",
-        "sample": f"FP64 oracle (numpy complex128 pairwise tensordot along the same tree) on slice 0 for "
-                  f"{len(vals)} bitstrings in {el:.1f} s, extrapolated x{n_slices} slices",
+        "sample": "FP64 oracle (numpy complex128 pairwise tensordot along the same tree): " + describe(done, el),
         "host_cpus": len(os.sched_getaffinity(0)),
         "cpu_model": cpu_model(),
         "blas": blas,
     }
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):
-            v1, el1 = sample(seconds / 3, len(xs))
-        out["single_thread"] = {"value": 1.0 / (el1 / len(v1) * n_slices), "unit": "amplitudes/s", "cores": 1,
-                                "sample": f"slice 0, {len(v1)} bitstrings in {el1:.1f} s, extrapolated "
-                                          f"x{n_slices} slices"}
+            _, d1, el1 = sample(seconds / 3)
+        out["single_thread"] = {"value": d1 / el1 / n_slices, "unit": "amplitudes/s", "cores": 1,
+                                "sample": describe(d1, el1)}
     return out, np.array(vals)
 
 

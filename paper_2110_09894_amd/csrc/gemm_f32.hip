@@ -12,8 +12,10 @@ namespace qx {
 // operands, which is a valid split of the k-sum.  A complex product is four
 // real MFMAs into separate real / imaginary accumulators.
 // ---------------------------------------------------------------------------
+// Tiles of 128x64 up to 128x128 are held to 256 registers per lane (accumulators in VGPRs), so two
+// work-groups share a CU: at 128x128 this took the c64 products from one to two waves per SIMD.
 template <int BM, int BN, bool A_KC, bool B_KC>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
+__global__ __launch_bounds__(256, (BM * BN > 64 * 64 && BM * BN <= 128 * 128) ? 2 : 1) void k_gemm_f32(GemmArgs p) {
   constexpr int BK = 16;
   constexpr int PITCH = BK + 2;            // complex per LDS row (+16 B against bank conflicts)
   constexpr int WM = BM / 2, WN = BN / 2;  // wave tile

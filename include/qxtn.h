@@ -88,7 +88,24 @@ typedef struct {
                                   yields the 2^m amplitudes of all values of those m qubits
                                   (Sec. II: output indices left open give a batch of amplitudes);
                                   m <= 16 and max_bitstrings * 2^m <= 2^24.  0 = all closed */
+  int32_t gemm_tile;           /* matrix-core work-group tile of every product: 0 = automatic (the
+                                  autotuner's choice when autotune is set, else a default by shape);
+                                  t + 1 = force qx_gemm_tile t for every product (autotune is then
+                                  ignored); other values are rejected */
+  int32_t reserved_;           /* must be 0 */
 } qx_plan_options;
+
+/* Work-group tile shapes (rows of A x columns of B) of the matrix-core products.
+ * Options and qx_cgemm take the tile as (value + 1), 0 meaning automatic. */
+typedef enum {
+  QX_TILE_128x128 = 0,
+  QX_TILE_64x64 = 1,
+  QX_TILE_128x64 = 2,
+  QX_TILE_64x128 = 3,
+  QX_TILE_256x128 = 4,
+  QX_TILE_128x256 = 5,
+  QX_N_TILES = 6
+} qx_gemm_tile;
 
 typedef struct {
   int64_t device_bytes;        /* device memory the plan holds (leaves, constants, arena) */
@@ -136,6 +153,28 @@ qx_status qx_plan_create(const qx_network *net, const int32_t *tree, const int64
 qx_status qx_plan_get_info(const qx_plan *plan, qx_plan_info *info);
 
 /*
+ * Device memory the same network, tree and slice set would hold as a plan with
+ * another bitstring capacity or slice batch (Sec. III-B: device memory is the
+ * second, tighter bottleneck; Sec. III-A: slicing trades memory for repeated
+ * work).  Host only: the plan is recompiled on the host with those two values
+ * (nothing is allocated on the device), so it is valid on dry-run plans and
+ * costs milliseconds; the figure is what qx_plan_get_info's device_bytes
+ * would report for that plan (leaves, constants, arena, gather tables, scale
+ * slots, slice-block state and FP64 accumulator), excluding the caller's
+ * bitstring and amplitude buffers (8 * B and 16 * B * 2^m bytes).
+ *
+ *   plan              any plan (dry-run or not); not modified.
+ *   n_bitstrings      0 = the plan's max_bitstrings, else 1..2^20 with
+ *                     n_bitstrings * 2^m <= 2^24.
+ *   slice_batch_log2  -1 = the plan's effective slice batch, else
+ *                     0..min(n_sliced, 24): 2^j slices computed per pass.
+ *   bytes             receives the figure.
+ * Errors: QX_ERR_INVALID_ARG (NULL pointer, value out of range).
+ */
+qx_status qx_plan_peak_bytes(const qx_plan *plan, int32_t n_bitstrings, int32_t slice_batch_log2,
+                             int64_t *bytes);
+
+/*
  * Accumulate amplitudes: for each of the B bitstrings x_b,
  *   d_amplitudes[b] += sum over slices s in [slice_begin, slice_end) of the value
  *                      of slice s's network closed by x_b        (Eq. 2, Sec. II)
@@ -161,7 +200,10 @@ qx_status qx_contract(qx_plan *plan, const uint64_t *d_bitstrings, int32_t B,
                       void *stream);
 
 /* Release every device and host resource of the plan (NULL is a no-op).
- * Synchronises the plan's device work first. */
+ * First waits for the plan's own device work: the pre-contraction at creation
+ * and the work enqueued by its last qx_contract call (an event recorded at the
+ * end of each call on the call's stream); other work on the device is not
+ * waited for. */
 void qx_plan_destroy(qx_plan *plan);
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -216,17 +258,19 @@ qx_status qx_permute_c64(const void *d_in, void *d_out, int32_t rank, const int3
  * Element (m, k) of A item z is at d_a + z*stride_a + m*a_ms + k*a_ks; one of
  * a_ms, a_ks must be 1.  B likewise with (k, n) strides b_ks, b_ns.  C item z
  * is dense row-major [M][N] at d_c + z*stride_c.  All strides in complex
- * elements.  precision: qx_precision.  M, N, K >= 1.  Asynchronous on stream.
+ * elements.  precision: qx_precision.  M, N, K >= 1.  tile: 0 = a default
+ * work-group tile by shape, t + 1 = qx_gemm_tile t (any tile is valid for any
+ * M, N).  Asynchronous on stream.
  * QX_SPLIT_BF16 first splits A and B into stream-ordered temporaries
  * (hipMallocAsync, 8*batch*(M+N)*roundup(K,16) bytes, freed on the stream);
  * the split-BF16 products of a plan read operands their producers stored
  * split and allocate nothing.  Errors: QX_ERR_INVALID_ARG (NULL pointer,
- * sizes, strides), QX_ERR_HIP (launch or allocation failure).
+ * sizes, strides, tile), QX_ERR_HIP (launch or allocation failure).
  */
 qx_status qx_cgemm(const void *d_a, const void *d_b, void *d_c, int64_t M, int64_t N, int64_t K,
                    int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a,
                    int64_t stride_b, int64_t stride_c, int64_t batch, int32_t precision,
-                   void *stream);
+                   int32_t tile, void *stream);
 
 #ifdef __cplusplus
 }

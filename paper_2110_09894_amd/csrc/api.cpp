@@ -69,6 +69,14 @@ struct qx_plan {
   bool eager = false;
   hipStream_t cap_stream = nullptr;   // stream used to capture block programs
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // per batch size
+  hipEvent_t done = nullptr;          // recorded after the plan's latest device work
+  // host copies of the compile inputs, so the plan can be recompiled with another
+  // bitstring capacity or slice batch (qx_plan_peak_bytes)
+  std::vector<int64_t> net_index_ptr, net_index_ids, net_data_ptr, net_output;
+  int32_t net_n_qubits = 0;
+  std::vector<int32_t> tree;
+  std::vector<int64_t> sliced;
+  qx_plan_options opt{};
 };
 
 static int64_t state_bytes(const PlanCore& pc) { return 64 + ((int64_t)pc.max_b << pc.n_open) * 16; }
@@ -332,6 +340,9 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
   return QX_OK;
 }
 
+static qx_status contract_enqueue(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64_t slice_begin,
+                                  int64_t slice_end, double* d_amplitudes, hipStream_t s);
+
 extern "C" {
 
 const char* qx_last_error(void) { return g_err.c_str(); }
@@ -355,8 +366,15 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     const int64_t r = net->index_ptr[t + 1] - net->index_ptr[t];
     if (r < 0 || r > 40) return fail(QX_ERR_UNSUPPORTED, "tensor rank must be in 0..40");
   }
-  qx_plan_options opt = {QX_C64, 1, -1, 0, 0, 0, 0, 0};
+  qx_plan_options opt;
+  std::memset(&opt, 0, sizeof(opt));
+  opt.precision = QX_C64;
+  opt.max_bitstrings = 1;
+  opt.slice_batch_log2 = -1;
   if (opt_in) opt = *opt_in;
+  if (opt.gemm_tile < 0 || opt.gemm_tile > GEMM_N_TILES)
+    return fail(QX_ERR_INVALID_ARG, "gemm_tile must be 0 (automatic) or 1..6 (tile + 1)");
+  if (opt.reserved_ != 0) return fail(QX_ERR_INVALID_ARG, "reserved_ must be 0");
   if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
     return fail(QX_ERR_INVALID_ARG, "unknown precision");
   if (opt.max_bitstrings < 1 || opt.max_bitstrings > (1 << 20))
@@ -412,6 +430,24 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
   }
   p->dry = opt.dry_run != 0;
   p->eager = opt.eager != 0;
+  if (opt.gemm_tile > 0)
+    for (Op& op : p->pc.ops)
+      if (op.kind == OP_GEMM) op.tile = opt.gemm_tile - 1;
+  {
+    const int n = net->n_tensors;
+    p->net_index_ptr.resize(n + 1);
+    p->net_data_ptr.resize(n + 1);
+    for (int t = 0; t <= n; ++t) {
+      p->net_index_ptr[t] = net->index_ptr[t] - net->index_ptr[0];
+      p->net_data_ptr[t] = net->data_ptr[t] - net->data_ptr[0];
+    }
+    p->net_index_ids.assign(net->index_ids + net->index_ptr[0], net->index_ids + net->index_ptr[n]);
+    p->net_n_qubits = net->n_qubits;
+    p->net_output.assign(net->output_index, net->output_index + net->n_qubits);
+    if (n > 1) p->tree.assign(tree, tree + 2 * (n - 1));
+    p->sliced.assign(sliced, sliced + n_sliced);
+    p->opt = opt;
+  }
   for (const Op& op : p->pc.ops)
     if (op.kind != OP_SIMT && (!op.fix_a.empty() || !op.fix_b.empty())) {
       delete p;
@@ -476,7 +512,9 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("plan pre-contraction: ") + hipGetErrorString(e));
-    if (opt.autotune) {
+    if ((e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess)
+      return cleanup(QX_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    if (opt.autotune && opt.gemm_tile == 0) {
       // gather offsets of zero keep every timing launch's reads inside its operands
       if ((e = hipMemsetAsync(p->d_gather, 0, gb, s)) != hipSuccess)
         return cleanup(QX_ERR_HIP, std::string("hipMemsetAsync(gather): ") + hipGetErrorString(e));
@@ -515,6 +553,39 @@ qx_status qx_plan_get_info(const qx_plan* p, qx_plan_info* info) {
   return QX_OK;
 }
 
+qx_status qx_plan_peak_bytes(const qx_plan* p, int32_t n_bitstrings, int32_t slice_batch_log2, int64_t* bytes) {
+  g_err.clear();
+  if (!p || !bytes) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  const int B = n_bitstrings == 0 ? p->pc.max_b : n_bitstrings;
+  if (B < 1 || B > (1 << 20)) return fail(QX_ERR_INVALID_ARG, "n_bitstrings must be 0 or in 1..2^20");
+  if (((int64_t)B << p->pc.n_open) > ((int64_t)1 << 24))
+    return fail(QX_ERR_INVALID_ARG, "n_bitstrings * 2^(open qubits) must be <= 2^24");
+  const int js = slice_batch_log2 < 0 ? p->pc.js : slice_batch_log2;
+  if (slice_batch_log2 < -1 || js > std::min(p->pc.n_sliced, QX_MAX_SBITS))
+    return fail(QX_ERR_INVALID_ARG, "slice_batch_log2 must be -1 or in 0..min(n_sliced, 24)");
+  if (B == p->pc.max_b && js == p->pc.js) {
+    *bytes = p->device_bytes;
+    return QX_OK;
+  }
+  qx_network net;
+  net.n_tensors = p->pc.n_leaves;
+  net.index_ptr = p->net_index_ptr.data();
+  net.index_ids = p->net_index_ids.data();
+  net.data_ptr = p->net_data_ptr.data();
+  net.data = p->pc.leaf_data.data();
+  net.n_qubits = p->net_n_qubits;
+  net.output_index = p->net_output.data();
+  qx_plan_options opt = p->opt;
+  opt.max_bitstrings = B;
+  PlanCore pc;
+  std::string err;
+  const qx_status st = compile_plan(&net, p->tree.empty() ? nullptr : p->tree.data(), p->sliced.data(),
+                                    (int32_t)p->sliced.size(), opt, js, pc, err);
+  if (st != QX_OK) return fail(st, err);
+  *bytes = plan_device_bytes(pc);
+  return QX_OK;
+}
+
 qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64_t slice_begin,
                       int64_t slice_end, double* d_amplitudes, void* stream) {
   g_err.clear();
@@ -533,6 +604,19 @@ qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64
   HIP_TRY(hipGetDevice(&cur));
   if (cur != p->device) return fail(QX_ERR_INVALID_ARG, "current device differs from the plan's device");
   hipStream_t s = (hipStream_t)stream;
+  const qx_status st = contract_enqueue(p, d_bitstrings, B, slice_begin, slice_end, d_amplitudes, s);
+  // whatever was enqueued, qx_plan_destroy waits for it through this event
+  const hipError_t e = hipEventRecord(p->done, s);
+  if (st == QX_OK && e != hipSuccess) return fail(QX_ERR_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+  return st;
+}
+
+}  // extern "C"
+
+// Enqueues one validated qx_contract call on stream s.
+static qx_status contract_enqueue(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64_t slice_begin,
+                                  int64_t slice_end, double* d_amplitudes, hipStream_t s) {
+  const PlanCore& pc = p->pc;
   for (size_t g = 0; g < pc.gathers.size(); ++g) {
     const GatherDesc& gd = pc.gathers[g];
     GatherArgs ga;
@@ -600,6 +684,8 @@ qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64
   return QX_OK;
 }
 
+extern "C" {
+
 qx_status qx_plan_set_timing(qx_plan* p, int32_t enable) {
   g_err.clear();
   if (!p) return fail(QX_ERR_INVALID_ARG, "plan is NULL");
@@ -635,7 +721,9 @@ void qx_plan_destroy(qx_plan* p) {
     int cur = 0;
     hipGetDevice(&cur);
     hipSetDevice(p->device);
-    hipDeviceSynchronize();
+    // the plan's own work only: the last contract call (or the creation) recorded p->done
+    if (p->done) hipEventSynchronize(p->done);
+    if (p->cap_stream) hipStreamSynchronize(p->cap_stream);
     for (PendingEvent& ev : p->pending) {
       hipEventDestroy(ev.a);
       hipEventDestroy(ev.b);
@@ -651,6 +739,7 @@ void qx_plan_destroy(qx_plan* p) {
       hipGraphDestroy(kv.second.first);
     }
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    if (p->done) hipEventDestroy(p->done);
     hipSetDevice(cur);
   }
   delete p;
@@ -684,9 +773,10 @@ qx_status qx_permute_c64(const void* d_in, void* d_out, int32_t rank, const int3
 
 qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K, int64_t a_ms,
                    int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a, int64_t stride_b,
-                   int64_t stride_c, int64_t batch, int32_t precision, void* stream) {
+                   int64_t stride_c, int64_t batch, int32_t precision, int32_t tile_opt, void* stream) {
   g_err.clear();
   if (!d_a || !d_b || !d_c) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..6");
   if (M < 1 || N < 1 || K < 1 || batch < 0) return fail(QX_ERR_INVALID_ARG, "M, N, K must be >= 1, batch >= 0");
   if (!(a_ms == 1 || a_ks == 1) || !(b_ks == 1 || b_ns == 1) || a_ms < 1 || a_ks < 1 || b_ks < 1 || b_ns < 1)
     return fail(QX_ERR_INVALID_ARG, "one stride of each operand must be 1 and all strides >= 1");
@@ -707,7 +797,7 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
   hipStream_t s = (hipStream_t)stream;
-  const int tile = gemm_default_tile(M, N);
+  const int tile = tile_opt > 0 ? tile_opt - 1 : gemm_default_tile(M, N);
   if (precision != QX_SPLIT_BF16) {
     gemm_args_setup(g);
     HIP_TRY(launch_gemm(g, precision, tile, s));

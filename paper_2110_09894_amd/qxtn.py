@@ -28,8 +28,19 @@ QX_SPLIT_BF16 = 1
 QX_SPLIT_FP16 = 2
 PRECISIONS = {"c64": QX_C64, "split_bf16": QX_SPLIT_BF16, "split_fp16": QX_SPLIT_FP16}
 
-EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_contract", "qx_plan_destroy", "qx_last_error",
-            "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm"]
+EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_plan_peak_bytes", "qx_contract", "qx_plan_destroy",
+            "qx_last_error", "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm"]
+
+# matrix-core work-group tiles (qx_gemm_tile order); options take index + 1, 0 = automatic
+TILES = ["128x128", "64x64", "128x64", "64x128", "256x128", "128x256"]
+
+
+def _tile_opt(tile):
+    if tile is None or tile == 0:
+        return 0
+    if isinstance(tile, str):
+        return TILES.index(tile) + 1
+    raise ValueError("tile must be None or one of " + ", ".join(TILES))
 
 OPCLASSES = ["gemm", "simt", "dot", "permute", "slice_sum", "gather", "scale"]
 
@@ -51,7 +62,7 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_bitstrings", C.c_int32),
                 ("slice_batch_log2", C.c_int32), ("dry_run", C.c_int32),
                 ("hbm_budget_bytes", C.c_int64), ("autotune", C.c_int32), ("eager", C.c_int32),
-                ("open_qubits", C.c_uint64)]
+                ("open_qubits", C.c_uint64), ("gemm_tile", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -84,6 +95,8 @@ def lib():
                                      C.POINTER(_Options), C.c_void_p, C.POINTER(C.c_void_p)]
         L.qx_plan_get_info.restype = C.c_int
         L.qx_plan_get_info.argtypes = [C.c_void_p, C.POINTER(PlanInfo)]
+        L.qx_plan_peak_bytes.restype = C.c_int
+        L.qx_plan_peak_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.qx_contract.restype = C.c_int
         L.qx_contract.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]
         L.qx_plan_destroy.restype = None
@@ -97,7 +110,8 @@ def lib():
         L.qx_permute_c64.restype = C.c_int
         L.qx_permute_c64.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int64, C.c_void_p]
         L.qx_cgemm.restype = C.c_int
-        L.qx_cgemm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int64] * 11 + [C.c_int32, C.c_void_p]
+        L.qx_cgemm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int64] * 11 + [C.c_int32, C.c_int32,
+                                                                                         C.c_void_p]
         _lib = L
     return _lib
 
@@ -133,7 +147,8 @@ class Plan:
     """Owns a qx_plan handle (qx_plan_create / qx_plan_destroy)."""
 
     def __init__(self, network, tree, sliced=(), precision="c64", max_bitstrings=1, slice_batch_log2=-1,
-                 dry_run=False, hbm_budget_bytes=0, autotune=False, eager=False, open_qubits=(), stream=None):
+                 dry_run=False, hbm_budget_bytes=0, autotune=False, eager=False, open_qubits=(), gemm_tile=None,
+                 stream=None):
         index_ptr, index_ids, data_ptr, data, output_index = network.to_csr()
         self._keep = [np.ascontiguousarray(index_ptr, np.int64), np.ascontiguousarray(index_ids, np.int64),
                       np.ascontiguousarray(data_ptr, np.int64), np.ascontiguousarray(data, np.float64),
@@ -148,7 +163,7 @@ class Plan:
         for q in open_qubits:
             mask |= 1 << int(q)
         opt = _Options(prec, int(max_bitstrings), int(slice_batch_log2), int(bool(dry_run)), int(hbm_budget_bytes),
-                       int(bool(autotune)), int(bool(eager)), mask)
+                       int(bool(autotune)), int(bool(eager)), mask, _tile_opt(gemm_tile), 0)
         h = C.c_void_p()
         _check(lib().qx_plan_create(C.byref(net), _ptr(tr, C.c_int32) if tr.size else None,
                                     _ptr(sl, C.c_int64) if sl.size else None, len(sl), C.byref(opt),
@@ -165,6 +180,12 @@ class Plan:
         inf = PlanInfo()
         _check(lib().qx_plan_get_info(self.handle, C.byref(inf)))
         return inf.as_dict()
+
+    def peak_bytes(self, n_bitstrings=0, slice_batch_log2=-1) -> int:
+        """Device bytes of this plan recompiled for another bitstring capacity / slice batch (host only)."""
+        out = C.c_int64()
+        _check(lib().qx_plan_peak_bytes(self.handle, int(n_bitstrings), int(slice_batch_log2), C.byref(out)))
+        return out.value
 
     def contract(self, bitstrings, amplitudes, slice_range=None, stream=None):
         """amplitudes (float64 [B, 2^m, 2] contiguous, device; m open qubits, [B, 2] when none)
@@ -222,8 +243,8 @@ def permute_c64(x, out, in_pos, items=1, stream=None):
 
 
 def cgemm(a, b, c, M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a=0, stride_b=0, stride_c=0, batch=1,
-          precision="c64", stream=None):
+          precision="c64", tile=None, stream=None):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().qx_cgemm(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(c.data_ptr()),
                           M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a, stride_b, stride_c, batch, prec,
-                          _stream_handle(stream)))
+                          _tile_opt(tile), _stream_handle(stream)))

@@ -198,3 +198,44 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_bad_tile_option_rejected():
+    net, tree, sl = _small()
+    for t in qxtn.TILES:
+        qxtn.Plan(net, tree, sl, gemm_tile=t, dry_run=True)
+    with pytest.raises(ValueError):
+        qxtn.Plan(net, tree, sl, gemm_tile="32x32", dry_run=True)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c4"])
+def test_peak_bytes_matches_compiled_plans_and_is_monotone(cfg):
+    """qx_plan_peak_bytes (Sec. III-B: device memory as the second bottleneck) equals the device_bytes of the
+    plan compiled at each (B, slice batch) point, and grows with both."""
+    from workloads import configs
+    w = configs.get(cfg)
+    tree, sl, _ = w.plan_inputs()
+    B0 = w.n_bitstrings
+    p = qxtn.Plan(w.network(), tree, sl, max_bitstrings=B0, dry_run=True)
+    info = p.info()
+    assert p.peak_bytes() == info["device_bytes"]
+    assert p.peak_bytes(B0, info["slice_batch_log2"]) == info["device_bytes"]
+    bs = sorted({1, 2, 7, 64, B0, 4 * B0})
+    js_all = list(range(0, min(len(sl), 8) + 1))
+    grid = {}
+    for B in bs:
+        for js in js_all:
+            got = p.peak_bytes(B, js)
+            if (B, js) in [(bs[0], js_all[0]), (B0, js_all[-1]), (bs[-1], js_all[len(js_all) // 2])]:
+                q = qxtn.Plan(w.network(), tree, sl, max_bitstrings=B, slice_batch_log2=js, dry_run=True)
+                assert got == q.info()["device_bytes"], (B, js)
+            grid[B, js] = got
+    for i, B in enumerate(bs):
+        for j, js in enumerate(js_all):
+            if i:
+                assert grid[B, js] >= grid[bs[i - 1], js], (B, js)
+            if j:
+                assert grid[B, js] >= grid[B, js_all[j - 1]], (B, js)
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(-1))
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(0, len(sl) + 1))
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(0, -2))

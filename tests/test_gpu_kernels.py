@@ -50,7 +50,7 @@ def test_permute_identity_and_reversal():
         assert np.array_equal(_host_c64(out).reshape(-1), want.reshape(-1))
 
 
-def _gemm_case(M, N, K, akc, bkc, batch, seed, precision="c64"):
+def _gemm_case(M, N, K, akc, bkc, batch, seed, precision="c64", tile=None):
     rng = np.random.default_rng(seed)
     A = _c64(rng, batch, M, K)
     Bm = _c64(rng, batch, K, N)
@@ -60,7 +60,7 @@ def _gemm_case(M, N, K, akc, bkc, batch, seed, precision="c64"):
     b_ks, b_ns = (1, K) if bkc else (N, 1)
     dc = torch.zeros(batch * M * N * 2, dtype=torch.float32, device="cuda")
     qxtn.cgemm(_dev(a_store), _dev(b_store), dc, M, N, K, a_ms, a_ks, b_ks, b_ns, M * K, K * N, M * N, batch,
-               precision)
+               precision, tile=tile)
     torch.cuda.synchronize()
     got = _host_c64(dc).reshape(batch, M, N).astype(np.complex128)
     want = np.matmul(A.astype(np.complex128), Bm.astype(np.complex128))
@@ -93,3 +93,30 @@ def test_cgemm_split(precision, M, N, K, akc, bkc):
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert rel < SPLIT_REL[precision], rel
     assert np.all(np.abs(got - want) <= 64 * SPLIT_REL[precision] * bound + 1e-30)
+
+
+@pytest.mark.parametrize("tile", qxtn.TILES)
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("M,N,K,akc,bkc", [(300, 129, 257, True, True), (512, 384, 64, False, False),
+                                           (37, 53, 19, True, False), (64, 96, 24, False, True),
+                                           (256, 256, 128, True, True), (1, 1, 1, True, True)])
+def test_cgemm_every_tile(tile, precision, M, N, K, akc, bkc):
+    """Every work-group tile the autotuner may pick, forced, in every precision: shapes spanning several
+    tiles, ragged edges in m, n and k, tiles larger than the matrix."""
+    got, want, bound = _gemm_case(M, N, K, akc, bkc, 2, M * 13 + N * 7 + K, precision, tile)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    if precision == "c64":
+        assert np.all(np.abs(got - want) <= 2 * K * 2.0 ** -23 * bound + 1e-30)
+        assert rel < 2e-6
+    else:
+        assert rel < SPLIT_REL[precision], rel
+        assert np.all(np.abs(got - want) <= 64 * SPLIT_REL[precision] * bound + 1e-30)
+
+
+def test_cgemm_tile_argument_validated():
+    a = torch.zeros(64, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        qxtn.cgemm(a, a, a, 4, 4, 4, 4, 1, 1, 4, tile="16x16")
+    # the C-ABI itself rejects tiles outside 0..6 before launching anything
+    st = qxtn.lib().qx_cgemm(a.data_ptr(), a.data_ptr(), a.data_ptr(), 4, 4, 4, 4, 1, 1, 4, 0, 0, 0, 1, 0, 7, None)
+    assert st == qxtn.QX_ERR_INVALID_ARG

@@ -235,30 +235,52 @@ def test_graph_replays_match_eager_bitwise():
     assert rms_err(want, oracle.amplitudes_statevector(circ, xs)) < TOL_C64
 
 
-def test_autotuned_plan_matches_oracle():
+@pytest.fixture(scope="module")
+def c2_slice777():
+    """The c2 workload and the oracle's values of slice 777 for its 256 bitstrings."""
     w = configs.get("c2")
     net = w.network()
     tree, sl, _ = w.plan_inputs()
     xs = w.bitstrings()
-    plan = qxtn.Plan(net, tree, sl, max_bitstrings=len(xs), autotune=True)
-    got = gpu_amplitudes(plan, xs, (777, 778))
     want = np.array([oracle.contract_slice(net, tree, x, sl, 777) for x in xs])
-    assert rms_err(got, want) < TOL_C64
+    return w, tree, sl, xs, want
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT), ("split_fp16", TOL_SPLIT)])
+def test_autotuned_plan_matches_oracle(c2_slice777, precision, tol):
+    """The launch configuration bench.py times (autotuned tiles, graph-replayed slice blocks), per precision."""
+    w, tree, sl, xs, want = c2_slice777
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs), autotune=True, precision=precision)
+    got = gpu_amplitudes(plan, xs, (777, 778))
+    assert rms_err(got, want) < tol
+
+
+@pytest.mark.parametrize("tile", qxtn.TILES)
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT), ("split_fp16", TOL_SPLIT)])
+def test_c2_slice_every_forced_tile(c2_slice777, tile, precision, tol):
+    """Every product of the 30-qubit plan run with one forced work-group tile, in every precision."""
+    w, tree, sl, xs, want = c2_slice777
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs), precision=precision, gemm_tile=tile)
+    got = gpu_amplitudes(plan, xs, (777, 778))
+    assert rms_err(got, want) < tol
 
 
 CHAIN_TREE = [(0, 1), (4, 2), (5, 3)]
 
 
+@pytest.mark.parametrize("tile", [None] + qxtn.TILES)
 @pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("order", [(True, True, True, True), (True, False, True, False), (False, False, False, False)])
 @pytest.mark.parametrize("sliced,js", [((), 0), ((5, 12), 2)])
-def test_dense_leaves_as_matrix_product_operands(precision, order, sliced, js):
+def test_dense_leaves_as_matrix_product_operands(precision, order, sliced, js, tile):
     """Dense random leaves read directly by matrix-core products: leaves whose
     summed labels are (or are not) their fastest-varying ones, a product fed by a
-    small contraction, and a varying sliced index shared by both operands."""
+    small contraction, and a varying sliced index shared by both operands; every
+    work-group tile forced in turn."""
     net = dense_chain_network(5, order, seed=11)
     xs = random_bitstrings(10, 16, 12)
-    plan = qxtn.Plan(net, CHAIN_TREE, list(sliced), max_bitstrings=64, precision=precision, slice_batch_log2=js)
+    plan = qxtn.Plan(net, CHAIN_TREE, list(sliced), max_bitstrings=64, precision=precision, slice_batch_log2=js,
+                     gemm_tile=tile)
     got = gpu_amplitudes(plan, xs)
     want = oracle.amplitudes_sliced(net, CHAIN_TREE, xs, list(sliced))
     assert rms_err(got, want) < (TOL_C64 if precision == "c64" else TOL_SPLIT)

@@ -62,10 +62,11 @@ def tree_stats(net, tree, sliced=()):
             "total_flops": flops * 2 ** len(sliced), "steps": steps}
 
 
-def greedy_tree(net, seed=0, alpha=1.0, temperature=0.0):
-    """One seeded greedy trial.  Returns an int32 SSA tree."""
+def greedy_tree(net, seed=0, alpha=1.0, temperature=0.0, exclude=()):
+    """One seeded greedy trial.  Returns an int32 SSA tree.  Labels in ``exclude`` (e.g. sliced ones,
+    whose values are fixed) do not count towards sizes."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    sets = _base_sets(net)
+    sets = _base_sets(net, exclude)
     n = len(sets)
     active = {}
     where = {}

@@ -272,6 +272,31 @@ qx_status qx_cgemm(const void *d_a, const void *d_b, void *d_c, int64_t M, int64
                    int64_t stride_b, int64_t stride_c, int64_t batch, int32_t precision,
                    int32_t tile, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the product of
+ * qx_cgemm, same arguments and same kernels, allocating nothing.  The
+ * split-BF16 operand copies that qx_cgemm puts in stream-ordered allocations
+ * go to a scratch array compiled into the library instead: each device the
+ * library runs on holds QX_CGEMM_NOALLOC_SCRATCH_BYTES of it until the process
+ * ends.  QX_C64 and QX_SPLIT_FP16 use no scratch.
+ *   Limit: with QX_SPLIT_BF16, 8 * batch * (M + N) * roundup(K, 16) bytes must
+ *   not exceed QX_CGEMM_NOALLOC_SCRATCH_BYTES, else QX_ERR_INVALID_ARG before
+ *   anything is enqueued.
+ *   Sharing: every call on a device uses that device's one scratch, which keeps
+ *   the last call's contents (each call overwrites all it reads); calls whose
+ *   work overlaps in time on one device (other streams, other host threads)
+ *   race and must be serialised, e.g. on one stream.
+ *   Set-up: the first call made with a device current looks up that device's
+ *   scratch address (hipGetSymbolAddress); no call allocates or frees memory.
+ * Other errors as qx_cgemm.
+ */
+#define QX_CGEMM_NOALLOC_SCRATCH_BYTES (64LL << 20)
+qx_status qx_cgemm_noalloc(const void *d_a, const void *d_b, void *d_c, int64_t M, int64_t N, int64_t K,
+                           int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a,
+                           int64_t stride_b, int64_t stride_c, int64_t batch, int32_t precision,
+                           int32_t tile, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

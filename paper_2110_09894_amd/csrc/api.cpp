@@ -771,10 +771,17 @@ qx_status qx_permute_c64(const void* d_in, void* d_out, int32_t rank, const int3
   return QX_OK;
 }
 
-qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K, int64_t a_ms,
-                   int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a, int64_t stride_b,
-                   int64_t stride_c, int64_t batch, int32_t precision, int32_t tile_opt, void* stream) {
-  g_err.clear();
+// Shared by qx_cgemm and qx_cgemm_noalloc.  Split BF16 splits A and B into
+// temporaries first: in `scratch` when given (it holds at least
+// cgemm_split_bytes(...) bytes), else in stream-ordered allocations.
+static int64_t cgemm_split_bytes(int64_t M, int64_t N, int64_t K, int64_t batch) {
+  const int64_t kp = (K + 15) / 16 * 16;
+  return 8 * batch * (M + N) * kp;
+}
+
+static qx_status cgemm_check(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K,
+                             int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t batch,
+                             int32_t precision, int32_t tile_opt) {
   if (!d_a || !d_b || !d_c) return fail(QX_ERR_INVALID_ARG, "NULL argument");
   if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..6");
   if (M < 1 || N < 1 || K < 1 || batch < 0) return fail(QX_ERR_INVALID_ARG, "M, N, K must be >= 1, batch >= 0");
@@ -782,6 +789,13 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
     return fail(QX_ERR_INVALID_ARG, "one stride of each operand must be 1 and all strides >= 1");
   if (precision < QX_C64 || precision > QX_SPLIT_FP16) return fail(QX_ERR_INVALID_ARG, "unknown precision");
   if (batch > 0x7fffffff) return fail(QX_ERR_INVALID_ARG, "batch too large");
+  return QX_OK;
+}
+
+static qx_status cgemm_run(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K,
+                           int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a,
+                           int64_t stride_b, int64_t stride_c, int64_t batch, int32_t precision, int32_t tile_opt,
+                           hipStream_t s, uint16_t* scratch) {
   if (batch == 0) return QX_OK;
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -796,7 +810,6 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   // 16-byte vector loads along k need even strides and an aligned base
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
-  hipStream_t s = (hipStream_t)stream;
   const int tile = tile_opt > 0 ? tile_opt - 1 : gemm_default_tile(M, N);
   if (precision != QX_SPLIT_BF16) {
     gemm_args_setup(g);
@@ -807,16 +820,18 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
   // temporaries [item][row][kp] (k zero-padded to a multiple of 16) first
   const int64_t kp = (K + 15) / 16 * 16;
   const int64_t pa = batch * M * kp, pb = batch * N * kp;
-  uint16_t *ta = nullptr, *tb = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&ta, pa * 8, s));
-  hipError_t e = hipMallocAsync((void**)&tb, pb * 8, s);
-  if (e != hipSuccess) {
-    hipFreeAsync(ta, s);
-    return fail(QX_ERR_HIP, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  uint16_t *ta = scratch, *tb = scratch ? scratch + 4 * pa : nullptr;
+  if (!scratch) {
+    HIP_TRY(hipMallocAsync((void**)&ta, pa * 8, s));
+    hipError_t e = hipMallocAsync((void**)&tb, pb * 8, s);
+    if (e != hipSuccess) {
+      hipFreeAsync(ta, s);
+      return fail(QX_ERR_HIP, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
   }
   SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, (int32_t)batch};
   SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, (int32_t)batch};
-  e = launch_split_planes(sa, s);
+  hipError_t e = launch_split_planes(sa, s);
   if (e == hipSuccess) e = launch_split_planes(sb, s);
   if (e == hipSuccess) {
     g.a = (const QxCplx*)ta;
@@ -829,10 +844,74 @@ qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64
     gemm_args_setup(g);
     e = launch_gemm(g, precision, tile, s);
   }
-  hipFreeAsync(ta, s);
-  hipFreeAsync(tb, s);
+  if (!scratch) {
+    hipFreeAsync(ta, s);
+    hipFreeAsync(tb, s);
+  }
   if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("split-BF16 product: ") + hipGetErrorString(e));
   return QX_OK;
+}
+
+}  // extern "C"
+
+// Scratch of qx_cgemm_noalloc: the split-BF16 operand copies of one call.  Every
+// device the library runs on holds its own instance until the process ends.  Host
+// code must not pass this name to a kernel (on the host it is only a stand-in
+// for the symbol): the device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) uint16_t scratch[QX_CGEMM_NOALLOC_SCRATCH_BYTES / 2];
+
+static std::mutex g_scratch_mu;
+static std::map<int, uint16_t*> g_scratch;  // device -> address of its scratch
+
+// Address of the current device's scratch, looked up on the first call made
+// with that device current.
+static qx_status noalloc_scratch(uint16_t** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(QX_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch.emplace(dev, static_cast<uint16_t*>(ptr)).first;
+  }
+  *out = it->second;
+  return QX_OK;
+}
+
+extern "C" {
+
+qx_status qx_cgemm_noalloc(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K,
+                           int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a,
+                           int64_t stride_b, int64_t stride_c, int64_t batch, int32_t precision, int32_t tile_opt,
+                           void* stream) {
+  g_err.clear();
+  const qx_status st = cgemm_check(d_a, d_b, d_c, M, N, K, a_ms, a_ks, b_ks, b_ns, batch, precision, tile_opt);
+  if (st != QX_OK) return st;
+  uint16_t* scr = nullptr;
+  if (precision == QX_SPLIT_BF16 && batch > 0) {
+    const double need = 8.0 * (double)batch * ((double)M + (double)N) * (double)((K + 15) / 16 * 16);
+    if (need > (double)QX_CGEMM_NOALLOC_SCRATCH_BYTES)
+      return fail(QX_ERR_INVALID_ARG, "split-BF16 operand copies need " + std::to_string((int64_t)need) +
+                                          " bytes; the allocation-free product's scratch holds " +
+                                          std::to_string((int64_t)QX_CGEMM_NOALLOC_SCRATCH_BYTES));
+    const qx_status sst = noalloc_scratch(&scr);
+    if (sst != QX_OK) return sst;
+  }
+  return cgemm_run(d_a, d_b, d_c, M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a, stride_b, stride_c, batch, precision,
+                   tile_opt, (hipStream_t)stream, scr);
+}
+
+qx_status qx_cgemm(const void* d_a, const void* d_b, void* d_c, int64_t M, int64_t N, int64_t K, int64_t a_ms,
+                   int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t stride_a, int64_t stride_b,
+                   int64_t stride_c, int64_t batch, int32_t precision, int32_t tile_opt, void* stream) {
+  g_err.clear();
+  const qx_status st = cgemm_check(d_a, d_b, d_c, M, N, K, a_ms, a_ks, b_ks, b_ns, batch, precision, tile_opt);
+  if (st != QX_OK) return st;
+  return cgemm_run(d_a, d_b, d_c, M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a, stride_b, stride_c, batch, precision,
+                   tile_opt, (hipStream_t)stream, nullptr);
 }
 
 }  // extern "C"

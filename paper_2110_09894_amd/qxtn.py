@@ -29,7 +29,9 @@ QX_SPLIT_FP16 = 2
 PRECISIONS = {"c64": QX_C64, "split_bf16": QX_SPLIT_BF16, "split_fp16": QX_SPLIT_FP16}
 
 EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_plan_peak_bytes", "qx_contract", "qx_plan_destroy",
-            "qx_last_error", "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm"]
+            "qx_last_error", "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm",
+            "qx_cgemm_noalloc"]
+CGEMM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # matrix-core work-group tiles (qx_gemm_tile order); options take index + 1, 0 = automatic
 TILES = ["128x128", "64x64", "128x64", "64x128", "256x128", "128x256"]
@@ -112,6 +114,8 @@ def lib():
         L.qx_cgemm.restype = C.c_int
         L.qx_cgemm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int64] * 11 + [C.c_int32, C.c_int32,
                                                                                          C.c_void_p]
+        L.qx_cgemm_noalloc.restype = C.c_int
+        L.qx_cgemm_noalloc.argtypes = L.qx_cgemm.argtypes
         _lib = L
     return _lib
 
@@ -248,3 +252,13 @@ def cgemm(a, b, c, M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a=0, stride_b=0, stri
     _check(lib().qx_cgemm(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(c.data_ptr()),
                           M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a, stride_b, stride_c, batch, prec,
                           _tile_opt(tile), _stream_handle(stream)))
+
+
+def cgemm_noalloc(a, b, c, M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a=0, stride_b=0, stride_c=0, batch=1,
+                  precision="c64", tile=None, stream=None):
+    """qx_cgemm_noalloc: the same product as ``cgemm`` without any device allocation (split-BF16 operand
+    copies in the library's per-device scratch of CGEMM_NOALLOC_SCRATCH_BYTES)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().qx_cgemm_noalloc(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(c.data_ptr()),
+                                  M, N, K, a_ms, a_ks, b_ks, b_ns, stride_a, stride_b, stride_c, batch, prec,
+                                  _tile_opt(tile), _stream_handle(stream)))

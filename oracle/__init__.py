@@ -24,9 +24,9 @@ other two computations; none is "parity unpinned".
 """
 from .statevector import statevector, amplitudes_statevector
 from .bruteforce import amplitude_bruteforce
-from .tree_contract import contract_slice, amplitude_sliced, amplitudes_sliced, slice_values
+from .tree_contract import contract_slice, amplitude_sliced, amplitudes_sliced
 from .sampling import probabilities, empirical_supremum_sample, empirical_supremum_sample_groups
 
 __all__ = ["statevector", "amplitudes_statevector", "amplitude_bruteforce", "contract_slice",
-           "amplitude_sliced", "amplitudes_sliced", "slice_values", "probabilities",
+           "amplitude_sliced", "amplitudes_sliced", "probabilities",
            "empirical_supremum_sample", "empirical_supremum_sample_groups"]

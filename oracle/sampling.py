@@ -20,7 +20,9 @@ def probabilities(circuit):
     return np.abs(np.transpose(psi, list(range(n - 1, -1, -1))).reshape(-1)) ** 2
 
 
-def empirical_supremum_sample(probs, n_qubits, candidates, uniforms, n_samples, warmup=0):
+def empirical_supremum_sample(probs, n_qubits, candidates, uniforms, n_samples, warmup=0, return_bound=False):
+    """Kept samples and per-candidate decisions (-1 warm-up, 0 rejected, 1 accepted); with ``return_bound``
+    also the final bound M."""
     N = 2.0 ** n_qubits
     M = 1.0
     kept = []
@@ -37,11 +39,12 @@ def empirical_supremum_sample(probs, n_qubits, candidates, uniforms, n_samples, 
             if accept:
                 kept.append(int(x))
         M = max(M, r)
-    return np.array(kept, dtype=np.uint64), np.array(decisions, dtype=np.int8)
+    out = (np.array(kept, dtype=np.uint64), np.array(decisions, dtype=np.int8))
+    return out + (M,) if return_bound else out
 
 
 def empirical_supremum_sample_groups(probs, n_qubits, open_qubits, candidates, uniforms, choices, n_samples,
-                                     warmup=0):
+                                     warmup=0, return_bound=False):
     """Group rejection sampling with open outputs (an extension of Sec. III-B using the open-index
     contraction of Sec. II; not in the paper).  A candidate x names the group of the 2^m bitstrings that
     agree with x outside the m open qubits; groups are proposed uniformly (G = 2^(n - m) of them).  The
@@ -85,4 +88,5 @@ def empirical_supremum_sample_groups(probs, n_qubits, open_qubits, candidates, u
                         break
                 kept.append(pick)
         M = max(M, r)
-    return np.array(kept, dtype=np.uint64), np.array(decisions, dtype=np.int8)
+    out = (np.array(kept, dtype=np.uint64), np.array(decisions, dtype=np.int8))
+    return out + (M,) if return_bound else out

@@ -57,11 +57,6 @@ def contract_slice(net, tree, bitstring, sliced=(), slice_id=0) -> complex:
     return complex(root)
 
 
-def slice_values(net, tree, bitstring, sliced, slice_ids) -> np.ndarray:
-    return np.array([contract_slice(net, tree, bitstring, sliced, s) for s in slice_ids],
-                    dtype=np.complex128)
-
-
 def amplitude_sliced(net, tree, bitstring, sliced=(), slice_range=None) -> complex:
     """sum over slices in ``slice_range`` (default: all 2^k) of each slice's value."""
     k = len(sliced)

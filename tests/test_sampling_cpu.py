@@ -1,6 +1,7 @@
 """Rejection sampler (Sec. III-B): the product's host logic against the oracle's
 independent implementation on the same candidate / uniform streams (CPU only)."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_2110_09894_amd.sampling import rejection_sample
@@ -104,3 +105,134 @@ def test_oracle_group_sampler_is_exact_in_distribution():
     emp = np.bincount(got.astype(np.int64), minlength=64) / len(got)
     assert 0.5 * np.abs(emp - probs).sum() < 0.04
     assert np.all(dec[:200] == -1)
+
+
+# ---- hand-worked pins of the sampling oracle (Sec. III-B, reading 13) ---------------------------------
+# Dyadic probabilities over n = 2 qubits (N = 4) so every product below is exact:
+#   p = [1/16, 1/8, 5/16, 1/2]  ->  r = p N = [0.25, 0.5, 1.25, 2.0]
+P4 = np.array([0.0625, 0.125, 0.3125, 0.5])
+
+
+def test_oracle_sampler_hand_worked_sequence():
+    """warm-up 2, 4 samples.  M starts at 1; a candidate is accepted when u M < r (strict), M = max(M, r)
+    after every candidate; warm-up candidates are never kept.  Worked by hand:
+      i x  r     u       u*M (M before)    decision  M after  kept
+      0 0  0.25  0.125   warm-up           -1        1
+      1 1  0.5   0.25    warm-up           -1        1
+      2 1  0.5   0.625   0.625 >= 0.5      0         1
+      3 1  0.5   0.5     0.5 not < 0.5     0         1
+      4 0  0.25  0.1875  0.1875 < 0.25     1         1        [0]
+      5 3  2.0   0.875   0.875 < 2.0       1         2        [0, 3]
+      6 2  1.25  0.6875  1.375 >= 1.25     0         2
+      7 1  0.5   0.1875  0.375 < 0.5       1         2        [0, 3, 1]
+      8 2  1.25  0.5     1.0 < 1.25        1         2        [0, 3, 1, 2]  -> 4 samples, stop
+      9 3  (not reached)
+    Mistakes each decision catches: keeping warm-up candidates (i0), M starting at 0 or at the first r
+    (i2), a non-strict test (i3), M not raised by an accepted candidate (i6), not stopping (i9)."""
+    cand = np.array([0, 1, 1, 1, 0, 3, 2, 1, 2, 3], dtype=np.uint64)
+    u = np.array([0.125, 0.25, 0.625, 0.5, 0.1875, 0.875, 0.6875, 0.1875, 0.5, 0.0625])
+    kept, dec, M = oracle.empirical_supremum_sample(P4, 2, cand, u, 4, warmup=2, return_bound=True)
+    assert kept.tolist() == [0, 3, 1, 2]
+    assert dec.tolist() == [-1, -1, 0, 0, 1, 1, 0, 1, 1]
+    assert M == 2.0
+    # the product's sampler, on amplitudes sqrt(p) (|a|^2 N is then r up to rounding, which would decide
+    # the exact tie of i3, so there u = 0.53125) makes the same decisions and ends with the same M
+    u2 = u.copy()
+    u2[3] = 0.53125
+    got, info = rejection_sample(lambda c: np.sqrt(P4[c.astype(np.int64)]), 2, cand, u2, 4, warmup=2, batch=3)
+    assert got.tolist() == [0, 3, 1, 2]
+    assert info["decisions"].tolist() == [-1, -1, 0, 0, 1, 1, 0, 1, 1]
+    assert info["M"] == pytest.approx(2.0, rel=1e-15)
+
+
+def test_oracle_sampler_warmup_raises_the_bound():
+    """warm-up 1, 1 sample:
+      i x  r     u     u*M (M before)   decision  M after
+      0 3  2.0   0.5   warm-up          -1        2
+      1 2  1.25  0.75  1.5 >= 1.25      0         2      (accepted if warm-up left M at 1)
+      2 2  1.25  0.5   1.0 < 1.25       1         2      kept [2], stop"""
+    cand = np.array([3, 2, 2, 0], dtype=np.uint64)
+    u = np.array([0.5, 0.75, 0.5, 0.0625])
+    kept, dec, M = oracle.empirical_supremum_sample(P4, 2, cand, u, 1, warmup=1, return_bound=True)
+    assert kept.tolist() == [2] and dec.tolist() == [-1, 0, 1] and M == 2.0
+
+
+def test_oracle_group_sampler_hand_worked_sequence():
+    """Open qubit 0 of 2: a candidate names the group {x with bit 0 = 0, x with bit 0 = 1}; G = 2 groups,
+    P(lo) = p0 + p1 = 0.1875, P(hi) = p2 + p3 = 0.8125, r = P G = 0.375 / 1.625.  warm-up 1, 2 samples.
+      i x  group r      u      u*M (M before)       decision  member (first j with c P < cumulative p)
+      0 2  hi    1.625  0.25   warm-up              -1        M -> 1.625
+      1 1  lo    0.375  0.25   0.40625 >= 0.375     0
+      2 0  lo    0.375  0.125  0.203125 < 0.375     1         c = 0.5: c P = 0.09375; cum 0.0625, 0.1875 -> y = 1
+      3 3  hi    1.625  0.875  1.421875 < 1.625     1         c = 0.0625: c P = 0.05078125 < 0.3125 -> y = 2"""
+    cand = np.array([2, 1, 0, 3, 0], dtype=np.uint64)
+    u = np.array([0.25, 0.25, 0.125, 0.875, 0.0])
+    c = np.array([0.5, 0.5, 0.5, 0.0625, 0.5])
+    kept, dec, M = oracle.empirical_supremum_sample_groups(P4, 2, (0,), cand, u, c, 2, warmup=1, return_bound=True)
+    assert kept.tolist() == [1, 2]
+    assert dec.tolist() == [-1, 0, 1, 1]
+    assert M == 1.625
+
+
+def test_oracle_probabilities_bit_order_closed_forms():
+    """Bit q of the probability index is qubit q: X (= sqrt(X)^2) on qubit 0 of 3 qubits puts all
+    probability on index 1; sqrt(X) on qubit 2 gives p[0] = p[4] = 1/2; X on qubit 1 then sqrt(X) on
+    qubit 0 gives p[2] = p[3] = 1/2."""
+    from workloads.circuits import Circuit, SQRT_X
+    c = Circuit(3).add("sx", (0,), SQRT_X).add("sx", (0,), SQRT_X)
+    p = oracle.probabilities(c)
+    want = np.zeros(8)
+    want[1] = 1.0
+    assert np.allclose(p, want, atol=1e-15)
+    p = oracle.probabilities(Circuit(3).add("sx", (2,), SQRT_X))
+    want = np.zeros(8)
+    want[0] = want[4] = 0.5
+    assert np.allclose(p, want, atol=1e-15)
+    c = Circuit(3).add("sx", (1,), SQRT_X).add("sx", (1,), SQRT_X).add("sx", (0,), SQRT_X)
+    want = np.zeros(8)
+    want[2] = want[3] = 0.5
+    assert np.allclose(oracle.probabilities(c), want, atol=1e-15)
+
+
+def _planted_sampler(probs, n_qubits, cand, u, n_samples, warmup, mistake):
+    """The sampling rule of Sec. III-B with one planted mistake (CPU only): shows that the hand-worked
+    sequences above tell each of these readings apart from the oracle's.  (Raising M only on accepted
+    candidates, or testing against the bound after its update, is not a different rule: a candidate whose
+    ratio exceeds M is accepted whatever u < 1.)"""
+    N = 2.0 ** n_qubits
+    M = 0.0 if mistake == "M starts at 0" else 1.0
+    kept, dec = [], []
+    for i, (x, ui) in enumerate(zip(cand, u)):
+        if len(kept) >= n_samples and mistake != "no stop":
+            break
+        r = probs[int(x)] * N
+        if i < warmup and mistake != "keep warm-up":
+            dec.append(-1)
+        else:
+            ok = ui * M <= r if mistake == "non-strict" else ui * M < r
+            dec.append(int(ok))
+            if ok:
+                kept.append(int(x))
+            if mistake == "M only from accepted" and not ok:
+                continue
+        if mistake == "warm-up leaves M" and i < warmup:
+            continue
+        if mistake == "M frozen after warm-up" and i >= warmup:
+            continue
+        M = max(M, r)
+    return kept, dec
+
+
+@pytest.mark.parametrize("mistake", ["M starts at 0", "keep warm-up", "non-strict", "warm-up leaves M",
+                                     "M frozen after warm-up", "no stop"])
+def test_hand_worked_sampling_pins_catch_planted_mistakes(mistake):
+    cand = np.array([0, 1, 1, 1, 0, 3, 2, 1, 2, 3], dtype=np.uint64)
+    u = np.array([0.125, 0.25, 0.625, 0.5, 0.1875, 0.875, 0.6875, 0.1875, 0.5, 0.0625])
+    ok_a = _planted_sampler(P4, 2, cand, u, 4, 2, None) == ([0, 3, 1, 2], [-1, -1, 0, 0, 1, 1, 0, 1, 1])
+    cand_b = np.array([3, 2, 2, 0], dtype=np.uint64)
+    u_b = np.array([0.5, 0.75, 0.5, 0.0625])
+    ok_b = _planted_sampler(P4, 2, cand_b, u_b, 1, 1, None) == ([2], [-1, 0, 1])
+    assert ok_a and ok_b  # the unmutated rule reproduces both hand-worked sequences
+    bad_a = _planted_sampler(P4, 2, cand, u, 4, 2, mistake) != ([0, 3, 1, 2], [-1, -1, 0, 0, 1, 1, 0, 1, 1])
+    bad_b = _planted_sampler(P4, 2, cand_b, u_b, 1, 1, mistake) != ([2], [-1, 0, 1])
+    assert bad_a or bad_b, mistake

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -34,7 +35,7 @@ DTYPES = {"c64": "c64 (fp32 mfma)", "split_bf16": "bf16 hi+lo x3 (fp32 acc)", "s
 HBM_PEAK = 8.0e12
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "gemm_traffic_c2_30q_d12.md")
-KERNEL_NAMES = {"c64": "k_gemm_f32", "split_bf16": "k_gemm_bf16s", "split_fp16": "k_gemm_split"}
+KERNEL_NAMES = {"c64": "k_gemm_f32", "split_bf16": "k_gemm_bf16s", "split_fp16": "k_gemm_fp16s"}
 COPY_BYTES = 1 << 30
 
 
@@ -307,8 +308,26 @@ def refined_note(args):
     return note
 
 
+def c4_golden(args, sliced, x):
+    """Oracle values of slices 0..63 of the 49-qubit workload (tests/golden/c4_slices_<tree>.json, written by
+    tests/golden/make_c4_oracle.py from the FP64 oracle), or None if absent or for other inputs."""
+    kind = "greedy" if not args.reconfigure else ("refined" if (args.reconfigure, args.mem_weight) == (4, 16.0)
+                                                    else None)
+    if kind is None:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", f"c4_slices_{kind}.json")
+    try:
+        g = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if [int(v) for v in g["sliced"]] != [int(v) for v in sliced] or int(g["bitstring"]) != int(x):
+        return None
+    return np.array([complex(*g["values"][str(s)]) for s in range(64)])
+
+
 def c4_bench(args):
     """c4: a contiguous block of slices of the 49-qubit network for one bitstring."""
+    import math
     import torch
     from paper_2110_09894_amd import qxtn
     from workloads import configs
@@ -324,7 +343,7 @@ def c4_bench(args):
     bsz = 1 << info["slice_batch_log2"]
     n = max(bsz, (args.slices // bsz) * bsz)
     amp = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
-    plan.contract(x, amp, (0, bsz))  # warm-up: one block (captures the block program)
+    plan.contract(x, amp, (0, 2 * bsz))  # warm-up: two blocks (captures the block program)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.contract(x, amp, (0, n))
@@ -337,76 +356,271 @@ def c4_bench(args):
            "data": "synthetic (seeded circuit and bitstring)",
            "config": {"workload": f"c4: {w.description}{refined_note(args)}", "slices_timed": n, "slice_batch": bsz,
                       "tree_width": st["width"], "flops_per_slice": st["flops_per_slice"]},
-           "seconds": el, "complex_tflops": flops / el / 1e12,
+           "seconds": el, "timed": "one contract call over the block, graph-replayed slice blocks",
+           "complex_tflops": flops / el / 1e12,
            "frac_of_peak": flops / el / PEAKS[args.precision],
            "extrapolated_seconds_per_amplitude": el * total / n,
            "extrapolation_note": f"x{total // n} to all 2^{len(sliced)} slices"}
+    if args.precision != "c64":
+        out["mfma_util"] = 3 * flops / el / PEAKS[args.precision]
+    out["call_sequence"] = {args.precision: ["warmup", "timed"]}
+    out["planner"] = {"reconfigure": args.reconfigure, "mem_weight": args.mem_weight}
+    out["argv"] = " ".join(sys.argv[1:])
+    out["config"]["precision"] = args.precision
+    out["config"]["bitstrings"] = 1
+    if not args.no_timing:
+        # one more block with per-launch HIP events (eager launches): roofline of the dominant kernel
+        plan.set_timing(True)
+        plan.get_timing(reset=True)
+        a1 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        t1 = time.perf_counter()
+        plan.contract(x, a1, (0, bsz))
+        torch.cuda.synchronize()
+        ev = time.perf_counter() - t1
+        timing = plan.get_timing(reset=True)
+        plan.set_timing(False)
+        out.update(roofline_of(timing, args.precision, ev))
+        out["evented_block_ms"] = 1e3 * ev
+        out["call_sequence"][args.precision].append("evented")
+    gold = c4_golden(args, sliced, xs[0])
+    if gold is not None:
+        # the first block's sum (Eq. 2 over slices 0..63) against the oracle's; normalised by the root sum of
+        # squares of the oracle's slice values (the amplitude scale those slices contribute)
+        a64 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        plan.contract(x, a64, (0, 64))
+        torch.cuda.synchronize()
+        got = complex(*a64.cpu().numpy()[0])
+        want = complex(math.fsum(gold.real), math.fsum(gold.imag))
+        out["call_sequence"][args.precision].append("check")
+        out["error_vs_oracle"] = {"slices": "0..63", "bitstrings": 1,
+                                  "abs_over_rss": abs(got - want) / float(np.sqrt(np.sum(np.abs(gold) ** 2))),
+                                  "relative": abs(got - want) / abs(want)}
     print(json.dumps(out), flush=True)
 
 
-def summarize_trace(db_path, log_path):
-    """Kernel-time summary of a ``rocprofv3 --kernel-trace --stats`` run of bench.py (3 timed steps, 1 warm-up)."""
+FAMILY = {v: k for k, v in KERNEL_NAMES.items()}  # kernel family -> precision
+
+
+def _family(name):
+    for short in KERNEL_NAMES.values():
+        if f"qx::{short}<" in name:
+            return short
+    return None
+
+
+def _tile_of(name):
+    """Work-group tile from a matrix-product kernel name: the first two template arguments."""
+    args = name.split("<", 1)[1].split(">", 1)[0].split(",")
+    return f"{args[0].strip()}x{args[1].strip()}"
+
+
+def trace_calls(db_path):
+    """Dispatches of a rocprofv3 kernel trace grouped into qx_contract calls (every call ends with
+    k_block_finish; plan creation, pre-contraction and tile autotuning fall into the plan's first call):
+    {precision: [[(kernel name, duration ns), ...] per call]} by the matrix-product kernel family a call
+    launches."""
     import sqlite3
     con = sqlite3.connect(db_path)
     rows = con.execute("select name, duration from kernels order by start").fetchall()
+    calls, cur = {}, []
+    for name, dur in rows:
+        cur.append((name, dur))
+        if "k_block_finish" in name:
+            fams = {_family(n) for n, _ in cur} - {None}
+            prec = FAMILY[fams.pop()] if len(fams) == 1 else None
+            calls.setdefault(prec, []).append(cur)
+            cur = []
+    return rows, calls
+
+
+def bench_line(log_path):
+    line = None
+    for l in open(log_path):
+        if l.startswith("{"):
+            line = json.loads(l)
+    return line
+
+
+def _roofline_of_line(line, prec):
+    if line is None:
+        return None
+    if prec == line.get("config", {}).get("precision"):
+        return line.get("roofline")
+    return line.get(prec, {}).get("roofline")
+
+
+def summarize_trace(db_path, log_path, out_name):
+    """Kernel-time summary of a ``rocprofv3 --kernel-trace --stats`` run of bench.py: whole-run totals per
+    kernel, then the matrix-product kernels' average launch duration in the graph-replayed timed calls and
+    in the evented call, beside bench.py's own event figure."""
+    rows, calls = trace_calls(db_path)
+    line = bench_line(log_path)
     top = {}
     for name, dur in rows:
         t = top.setdefault(name, [0, 0.0])
         t[0] += 1
         t[1] += dur * 1e-6
     total = sum(v[1] for v in top.values())
-    # per kernel family, launches of the timed contract calls: a call is every dispatch after the previous
-    # call's k_block_finish up to its own (per-call products included, as in bench.py's events); the first
-    # call of each plan is the warm-up, which also holds that plan's autotuning trials
-    fam, calls, cur = {}, 0, []
-    for name, dur in rows:
-        if "k_block_finish" not in name:
-            cur.append((name, dur))
-            continue
-        calls += 1
-        if calls % 4 != 1:
-            for n, d in cur:
-                for short in KERNEL_NAMES.values():
-                    if f"qx::{short}<" in n:
-                        f = fam.setdefault(short, [0, 0.0])
-                        f[0] += 1
-                        f[1] += d * 1e-6
-        cur = []
-    line = None
-    for l in open(log_path):
-        if l.startswith("{"):
-            line = json.loads(l)
-    out = ["# Kernel time on the 30-qubit workload (5x6 grid, depth 12, 1024 slices, 256 bitstrings)", "",
-           "Command (repository root, one MI355X):", "", "```",
+    seq = line.get("call_sequence", {}) if line else {}
+    wl = line["config"]["workload"] if line else "?"
+    out = [f"# Kernel time: {wl}", "", "Command (repository root, one MI355X):", "", "```",
            "cd /tmp && export TMPDIR=/tmp",
-           "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace_c2 -o run -- python3 $R/bench.py --steps 3 "
-           "--warmup 1 --no-cpu-baseline --no-permute",
-           "python3 $R/bench.py --summarize-trace $R/gpurun_out/trace_c2/run_results.db $R/gpurun_out/trace_c2.log",
+           f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/<dir> -o run -- python3 $R/bench.py {line.get('argv', '')}"
+           f" > $R/gpurun_out/<dir>.log" if line else "",
+           f"python3 $R/bench.py --summarize-trace $R/gpurun_out/<dir>/run_results.db $R/gpurun_out/<dir>.log {out_name}",
            "```", "",
-           "The run makes a complex64 plan and a split-BF16 plan (both autotuned); each does 1 warm-up call (graph",
-           "replay) and 3 timed calls (launches bracketed by events).  Whole-run totals per kernel:", "",
+           "Whole-run totals per kernel (plan creation, tile autotuning, warm-up, timed and evented calls):", "",
            "| kernel | calls | total ms | average ms | % of run |", "|---|---:|---:|---:|---:|"]
-    for name, (n, ms) in sorted(top.items(), key=lambda kv: -kv[1][1])[:20]:
+    for name, (n, ms) in sorted(top.items(), key=lambda kv: -kv[1][1])[:24]:
         out.append(f"| `{name[:90]}` | {n} | {ms:.0f} | {ms / n:.3f} | {100 * ms / total:.1f} |")
-    out += ["", "Matrix-product kernels (all tile shapes) inside the timed calls, against what bench.py measured",
-            "with HIP events in the same run:", ""]
-    for prec, short in KERNEL_NAMES.items():
-        if short not in fam:
+    out += ["", "Matrix-product kernels (all tile shapes) per call kind: `timed` calls replay the captured slice-block",
+            "graph, the `evented` call launches eagerly with a HIP event pair around every launch (the launches",
+            "bench.py's roofline averages over):", ""]
+    for prec, cl in calls.items():
+        if prec is None or prec not in seq:
             continue
-        n, ms = fam[short]
-        r = None
-        if line is not None:
-            r = line.get("roofline") if prec == line["config"].get("precision") else line.get(prec, {}).get("roofline")
-        ev = f"bench.py: {r['avg_launch_ms']:.3f} ms per launch, {r['achieved']:.1f} TFLOP/s algorithmic = " \
-             f"{100 * r['frac']:.1f}% of {r['peak']:.1f} TFLOP/s (MFMA work {100 * r['mfma_util']:.1f}% of peak)" if r else ""
-        out.append(f"* `{short}` ({prec}): {n} launches, average {ms / n:.3f} ms.  {ev}")
-    if line is not None:
-        out += ["", "bench.py line of this run: c64 " + f"{line['value']:.1f} amplitudes/s"
-                + (f", split_bf16 {line['split_bf16']['value']:.1f} amplitudes/s" if "split_bf16" in line else "")]
-    path = os.path.join(PROFILES, "gemm_c2_30q_d12.md")
+        kinds = seq[prec]
+        if len(kinds) != len(cl):
+            out.append(f"* {prec}: {len(cl)} calls in the trace, {len(kinds)} in bench.py's sequence -- not matched")
+            continue
+        short = KERNEL_NAMES[prec]
+        for kind in ("timed", "evented"):
+            ds = [d for c, k in zip(cl, kinds) if k == kind for n, d in c if _family(n) == short]
+            ncall = sum(1 for k in kinds if k == kind)
+            if ds:
+                out.append(f"* `{short}` ({prec}), {kind} calls ({ncall}): {len(ds)} launches, average "
+                           f"{sum(ds) / len(ds) * 1e-6:.3f} ms, {sum(ds) * 1e-6 / ncall:.1f} ms per call")
+        r = _roofline_of_line(line, prec)
+        if r:
+            out.append(f"  * bench.py events: {r['avg_launch_ms']:.3f} ms per launch, {r['achieved']:.1f} TFLOP/s "
+                       f"algorithmic = {100 * r['frac']:.1f}% of {r['peak']:.1f} TFLOP/s (MFMA work "
+                       f"{100 * r['mfma_util']:.1f}% of peak)")
+    path = os.path.join(PROFILES, out_name)
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print(path)
+
+
+def summarize_products(db_path, log_path, out_name):
+    """Per-product table from a rocprofv3 kernel trace of bench.py and the plan's own op list
+    (qx_plan_get_op_info on a host-only plan of the same inputs): for every matrix product of a step, its
+    sizes, algorithmic flops and bytes, measured average duration over the graph-replayed timed calls,
+    achieved rate against the dtype's peak, and whether it is GEMM-bound (flops / peak > bytes / HBM peak,
+    executed flops for split precision)."""
+    from paper_2110_09894_amd import qxtn
+    from workloads import configs
+    rows, calls = trace_calls(db_path)
+    line = bench_line(log_path)
+    cfg = line["config"]
+    wname = cfg["workload"].split(":", 1)[0]
+    w = configs.get(wname)
+    pl = line.get("planner", {})
+    tree, sliced, st = w.plan_inputs(reconfigure=pl.get("reconfigure", 0), mem_weight=pl.get("mem_weight", 16.0))
+    B = cfg.get("bitstrings", 1)
+    n_open = cfg.get("open_qubits", 0)
+    open_q = list(range(w.n_qubits - n_open, w.n_qubits))
+    seq = line["call_sequence"]
+    out = [f"# Matrix products per step: {cfg['workload']}", "",
+           "Commands (repository root, one MI355X):", "", "```", "cd /tmp && export TMPDIR=/tmp",
+           f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/<dir> -o run -- python3 $R/bench.py {line.get('argv', '')}"
+           f" > $R/gpurun_out/<dir>.log",
+           f"python3 $R/bench.py --summarize-products $R/gpurun_out/<dir>/run_results.db $R/gpurun_out/<dir>.log "
+           f"{out_name}", "```", "",
+           "Durations are averages over every launch of the product in the graph-replayed timed calls (rocprofv3",
+           "kernel trace); sizes, flops and bytes come from the plan (`qx_plan_get_op_info`).  Complex flops are",
+           "8 M N K per product; bytes count each operand read once and the result written once.  `exec %` is the",
+           "executed MFMA work (3 real products per term for split precision) against the dtype's dense peak;",
+           "`bound` is `mfma` when flops / peak exceed bytes / 8 TB/s (GEMM-bound, Sec. IV-A's matrix-product",
+           "steps), else `hbm`.", ""]
+    for prec in [p for p in KERNEL_NAMES if p in seq and p in calls]:
+        kinds = seq[prec]
+        cl = calls[prec]
+        if len(kinds) != len(cl):
+            out += [f"{prec}: {len(cl)} calls in the trace against {len(kinds)} in bench.py's sequence; skipped", ""]
+            continue
+        sb = line[prec]["slice_batch"] if prec in line and "slice_batch" in line[prec] else cfg["slice_batch"]
+        plan = qxtn.Plan(w.network(), tree, sliced, precision=prec, max_bitstrings=B,
+                         slice_batch_log2=int(round(math.log2(sb))), open_qubits=open_q, dry_run=True)
+        ops = [o for o in plan.ops() if o["op_class"] == "gemm" and o["phase"] >= 1]
+        call_ops = [o for o in ops if o["phase"] == 1]
+        block_ops = [o for o in ops if o["phase"] == 2]
+        short = KERNEL_NAMES[prec]
+        agg = {}
+        n_timed = 0
+        for c, k in zip(cl, kinds):
+            if k != "timed":
+                continue
+            n_timed += 1
+            g = [(n, d) for n, d in c if _family(n) == short]
+            for j, (n, d) in enumerate(g):
+                if j < len(call_ops):
+                    key = ("call", j)
+                elif block_ops:
+                    key = ("block", (j - len(call_ops)) % len(block_ops))
+                else:
+                    continue
+                a = agg.setdefault(key, {"n": 0, "ns": 0.0, "tile": _tile_of(n)})
+                a["n"] += 1
+                a["ns"] += d
+        peak = PEAKS[prec]
+        mult = 1 if prec == "c64" else 3
+        total_ns = sum(a["ns"] for a in agg.values())
+        out += [f"## {prec} (`{short}`), {n_timed} timed calls", "",
+                "| # | phase | M | N | K | batch | tile | launches/step | GFLOP/launch | MB/launch | avg µs | TFLOP/s | "
+                "% of peak | exec % | bound | % of product time |",
+                "|---:|---|---:|---:|---:|---:|---|---:|---:|---:|---:|---:|---:|---:|---|---:|"]
+        gb_ns = gb_flops = 0.0
+        for key in sorted(agg, key=lambda k: -agg[k]["ns"]):
+            a = agg[key]
+            o = call_ops[key[1]] if key[0] == "call" else block_ops[key[1]]
+            avg = a["ns"] / a["n"] * 1e-9
+            rate = o["flops"] / avg
+            bound = "mfma" if mult * o["flops"] / peak > o["bytes"] / HBM_PEAK else "hbm"
+            if bound == "mfma":
+                gb_ns += a["ns"]
+                gb_flops += o["flops"] * a["n"]
+            out.append(f"| {key[1]} | {key[0]} | {o['M']} | {o['N']} | {o['K']} | {o['batch']} | {a['tile']} | "
+                       f"{a['n'] / n_timed:g} | {o['flops'] / 1e9:.1f} | {o['bytes'] / 1e6:.1f} | {avg * 1e6:.1f} | "
+                       f"{rate / 1e12:.1f} | {100 * rate / peak:.1f} | {100 * mult * rate / peak:.1f} | {bound} | "
+                       f"{100 * a['ns'] / total_ns:.1f} |")
+        if gb_ns:
+            r = gb_flops / (gb_ns * 1e-9)
+            out += ["", f"GEMM-bound products together: {100 * gb_ns / total_ns:.1f}% of the product time, "
+                        f"{r / 1e12:.1f} TFLOP/s useful = {100 * mult * r / peak:.1f}% of the dense MFMA peak in "
+                        f"executed work.  All products: {total_ns * 1e-6 / n_timed:.1f} ms per step."]
+        out.append("")
+        plan.destroy()
+    path = os.path.join(PROFILES, out_name)
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(path)
+
+
+def roofline_of(timing, precision, step_s, traffic=None):
+    """Roofline of the dominant kernel from one evented step: algorithmic flops per launch over the average
+    launch duration (HIP events on the launch's stream); plus the per-class device time of that step."""
+    out = {"time_by_class_ms_per_step": {k: 1e3 * v["seconds"] for k, v in timing.items()}}
+    g = timing["gemm"]
+    if g["launches"] == 0:
+        # no contraction reaches the matrix-core sizes: the call is a chain of small launches, bound by
+        # launch latency; report the kernel class that takes the most device time
+        dom = max(timing, key=lambda k: timing[k]["seconds"])
+        d = timing[dom]
+        kernel_s = sum(v["seconds"] for v in timing.values())
+        out["roofline"] = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                           "traffic": None, "kernel": f"{dom} (largest class; no matrix-core launches)",
+                           "launches_per_step": sum(v["launches"] for v in timing.values()),
+                           "kernel_ms_per_step": 1e3 * kernel_s, "kernel_share_of_step": kernel_s / step_s,
+                           "avg_launch_ms": 1e3 * d["seconds"] / max(1, d["launches"])}
+        return out
+    ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
+    out["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
+                       "unit": "TFLOP/s", "frac": ach / PEAKS[precision], "traffic": traffic,
+                       "kernel": KERNEL_NAMES[precision],
+                       "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
+                       "launches_per_step": g["launches"], "avg_launch_ms": 1e3 * g["seconds"] / g["launches"],
+                       "measured_on": "one extra step with per-launch HIP events (eager launches)"}
+    return out
 
 
 def main():
@@ -436,13 +650,19 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
     ap.add_argument("--permute-only", action="store_true", help="time only k_permute (2^26 elements)")
     ap.add_argument("--summarize-traffic", metavar="DIR", help="write the HBM traffic summary from counter runs")
-    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "LOG"), help="write the kernel-time summary")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "LOG", "OUT"),
+                    help="write the kernel-time summary profiles/OUT from a kernel trace and the bench log")
+    ap.add_argument("--summarize-products", nargs=3, metavar=("DB", "LOG", "OUT"),
+                    help="write the per-product table profiles/OUT from a kernel trace and the bench log")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_products:
+        summarize_products(*args.summarize_products)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -484,18 +704,34 @@ def main():
     open_q = list(range(w.n_qubits - args.open_qubits, w.n_qubits))
     per_x = 1 << args.open_qubits
 
+    # the oracle's sample (CPU baseline) first: its slice-0 values give each precision's error right after the
+    # precision is timed, so every plan is destroyed before the next one is made and each gets the device's memory
+    cb, ref = (None, None)
+    if not args.no_cpu_baseline:
+        cb, ref = cpu_baseline(w, tree, sliced, xs, args.cpu_seconds)
+
+    def err(pl):
+        k = len(ref)
+        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+        a0 = torch.zeros((k, per_x, 2), dtype=torch.float64, device="cuda")
+        pl.contract(x[:k], a0, (0, 1))
+        torch.cuda.synchronize()
+        # with open qubits, the value whose open bits equal the bitstring's own is the closed amplitude
+        own = [sum(((int(xs[b]) >> q) & 1) << i for i, q in enumerate(open_q)) for b in range(k)]
+        got = a0.cpu().numpy()[np.arange(k), own]
+        got = got[:, 0] + 1j * got[:, 1]
+        return {"slice": 0, "bitstrings": k, "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
+
     def run(precision):
-        """Plan, warm up, then time exactly args.steps full contractions."""
+        """Plan, warm up, time exactly args.steps full contractions (graph-replayed slice blocks, no per-launch
+        events), then one more contraction with every launch bracketed by HIP events (eager launches) for the
+        roofline and the per-class split; then the error on slice 0 against the oracle."""
         plan = qxtn.Plan(net, tree, sliced, precision=precision, max_bitstrings=B,
                          autotune=not args.no_autotune, open_qubits=open_q)
         info = plan.info()
         amp = torch.zeros((B, per_x, 2), dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             plan.contract(x, amp)
-        torch.cuda.synchronize()
-        if not args.no_timing:
-            plan.set_timing(True)
-            plan.get_timing(reset=True)
         starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         torch.cuda.synchronize()
@@ -506,45 +742,29 @@ def main():
             ends[i].record()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        timing = None
-        if not args.no_timing:
-            timing = plan.get_timing(reset=True)
-            plan.set_timing(False)
         lat = np.array([s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)])
         executed = info["flops_block"] * (n_slices >> info["slice_batch_log2"]) + info["flops_call"]
         r = {"value": B * per_x * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
              "complex_tflops": executed / (elapsed / args.steps) / 1e12,
              "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-             "slice_batch": 1 << info["slice_batch_log2"]}
-        if timing is not None and timing["gemm"]["launches"] == 0:
-            # no contraction reaches the matrix-core sizes: the call is a chain of small launches, bound by
-            # launch latency; report the kernel class that takes the most device time
-            dom = max(timing, key=lambda k: timing[k]["seconds"])
-            d = timing[dom]
-            kernel_s = sum(v["seconds"] for v in timing.values()) / args.steps
-            r["roofline"] = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                             "traffic": None, "kernel": f"{dom} (largest class; no matrix-core launches)",
-                             "launches_per_step": sum(v["launches"] for v in timing.values()) / args.steps,
-                             "kernel_ms_per_step": 1e3 * kernel_s,
-                             "kernel_share_of_step": kernel_s / (elapsed / args.steps),
-                             "avg_launch_ms": 1e3 * d["seconds"] / max(1, d["launches"])}
-        elif timing is not None:
-            g = timing["gemm"]
-            ach = g["flops"] / g["seconds"] if g["seconds"] > 0 else 0.0
-            r["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAKS[precision] / 1e12,
-                             "unit": "TFLOP/s", "frac": ach / PEAKS[precision],
-                             # counters were taken on the 30-qubit workload only
-                             "traffic": (measured_traffic(KERNEL_NAMES[precision])
-                                         if args.workload == "c2" and not args.reconfigure
-                                         and not args.open_qubits else None),
-                             "kernel": KERNEL_NAMES[precision],
-                             "mfma_util": ach * (1 if precision == "c64" else 3) / PEAKS[precision],
-                             "launches_per_step": g["launches"] / args.steps,
-                             "avg_launch_ms": 1e3 * g["seconds"] / max(1, g["launches"])}
-            r["time_by_class_ms_per_step"] = {k: 1e3 * v["seconds"] / args.steps for k, v in timing.items()}
-        return plan, r
+             "slice_batch": 1 << info["slice_batch_log2"], "timed_steps": "graph-replayed slice blocks"}
+        if not args.no_timing:
+            plan.set_timing(True)
+            plan.get_timing(reset=True)
+            t1 = time.perf_counter()
+            plan.contract(x, amp)
+            torch.cuda.synchronize()
+            ev_el = time.perf_counter() - t1
+            timing = plan.get_timing(reset=True)
+            plan.set_timing(False)
+            r.update(roofline_of(timing, precision, ev_el))
+            r["evented_step_ms"] = 1e3 * ev_el
+        if ref is not None:
+            r["error_vs_oracle"] = err(plan)
+        plan.destroy()
+        return r
 
-    plan, main = run(args.precision)
+    main = run(args.precision)
     out = {
         "metric": METRIC,
         "value": main["value"],
@@ -566,41 +786,38 @@ def main():
         "complex_tflops": main["complex_tflops"],
         "latency_ms": main["latency_ms"],
     }
-    for k in ("roofline", "time_by_class_ms_per_step"):
+    for k in ("roofline", "time_by_class_ms_per_step", "evented_step_ms", "timed_steps"):
         if k in main:
             out[k] = main[k]
-    split_plans = {}
+    # contract calls each plan makes, in order (read by the trace summaries)
+    calls = ["warmup"] * args.warmup + ["timed"] * args.steps + ([] if args.no_timing else ["evented"])
+    out["call_sequence"] = {args.precision: list(calls)}
+    if "roofline" in out and out["roofline"]["bound"] == "mfma":
+        # counters were taken on the 30-qubit workload only
+        if args.workload == "c2" and not args.reconfigure and not args.open_qubits:
+            out["roofline"]["traffic"] = measured_traffic(KERNEL_NAMES[args.precision])
+    if ref is not None:
+        calls.append("check")
+        out["call_sequence"][args.precision] = list(calls)
+        out["error_vs_oracle"] = main["error_vs_oracle"]
     if args.precision == "c64" and not args.no_split:
-        for prec in ("split_bf16",):
-            sp, r = run(prec)
-            split_plans[prec] = sp
+        for prec in ("split_bf16", "split_fp16"):
+            r = run(prec)
             r["speedup_vs_c64"] = r["value"] / main["value"]
+            out["call_sequence"][prec] = list(calls)
+            if "roofline" in r and r["roofline"]["bound"] == "mfma" and args.workload == "c2" \
+                    and not args.reconfigure and not args.open_qubits:
+                r["roofline"]["traffic"] = measured_traffic(KERNEL_NAMES[prec])
             out[prec] = r
 
     # index-permute primitive on its own (the workload's plan needs none): HBM roofline
     if not args.no_permute:
         out["permute"] = permute_measure()
 
-    # accuracy on slice 0 and the CPU baseline share the oracle sample
-    if not args.no_cpu_baseline:
-        cb, ref = cpu_baseline(w, tree, sliced, xs, args.cpu_seconds)
+    if cb is not None:
         out["cpu_baseline"] = cb
-        k = len(ref)
-        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
-
-        def err(pl):
-            a0 = torch.zeros((k, per_x, 2), dtype=torch.float64, device="cuda")
-            pl.contract(x[:k], a0, (0, 1))
-            torch.cuda.synchronize()
-            # with open qubits, the value whose open bits equal the bitstring's own is the closed amplitude
-            own = [sum(((int(xs[b]) >> q) & 1) << i for i, q in enumerate(open_q)) for b in range(k)]
-            got = a0.cpu().numpy()[np.arange(k), own]
-            got = got[:, 0] + 1j * got[:, 1]
-            return {"slice": 0, "bitstrings": k, "max_abs_over_rms": float(np.max(np.abs(got - ref)) / scale)}
-
-        out["error_vs_oracle"] = err(plan)
-        for prec, sp in split_plans.items():
-            out[prec]["error_vs_oracle"] = err(sp)
+    out["planner"] = {"reconfigure": args.reconfigure, "mem_weight": args.mem_weight}
+    out["argv"] = " ".join(sys.argv[1:])
     print(json.dumps(out), flush=True)
 
 

@@ -53,7 +53,11 @@ typedef enum {
 typedef enum {
   QX_C64 = 0,        /* complex64 storage, FP32 MFMA matrix products */
   QX_SPLIT_BF16 = 1, /* matrix products as BF16 hi+lo terms on MFMA, FP32 accumulation */
-  QX_SPLIT_FP16 = 2  /* matrix products as FP16 hi+lo terms on MFMA, FP32 accumulation */
+  QX_SPLIT_FP16 = 2  /* matrix products as FP16 hi+lo terms on MFMA, FP32 accumulation; each
+                        operand tensor is stored times a power-of-two scale fixed at plan creation
+                        by a complex64 calibration pass (its largest magnitude then lies below 2^6,
+                        about 1000x below FP16's limit; a later value beyond that headroom gives
+                        non-finite amplitudes) */
 } qx_precision;
 
 /* The network: leaves only.  Output wires are open indices, not tensors. */
@@ -230,6 +234,25 @@ typedef struct {
   double bytes;     /* algorithmic bytes (each operand read once, result written once) */
 } qx_op_timing;
 
+/* One device operation of a compiled plan (host only; valid for dry-run plans). */
+typedef struct {
+  int32_t phase;     /* 0 run once at plan creation, 1 once per qx_contract call, 2 once per slice block */
+  int32_t op_class;  /* qx_opclass */
+  int64_t M, N, K;   /* matrix product: C[M][N] += A[M][K] B[K][N]; other ops: output elements, 1, summed
+                        elements (K = 1 for permutes and magnitude reductions) */
+  int64_t batch;     /* independent products per launch at max_bitstrings (bitstring items times
+                        shared varying-slice combinations) */
+  int32_t tile;      /* qx_gemm_tile the product launches with (autotuned or forced), -1 otherwise */
+  int32_t batched;   /* the op's batch scales with the call's B (one copy per bitstring) */
+  double flops;      /* algorithmic complex flops at max_bitstrings (8 M N K batch for products) */
+  double bytes;      /* algorithmic bytes at max_bitstrings (operands read once, result written once) */
+} qx_op_info;
+
+/* Ops are numbered in launch order: index 0 .. n_ops_const + n_ops_call + n_ops_block - 1 (qx_plan_info);
+ * the plan-time ops first, then the per-call ops, then the per-block ops.  QX_ERR_INVALID_ARG for an index
+ * out of range. */
+qx_status qx_plan_get_op_info(const qx_plan *plan, int32_t index, qx_op_info *info);
+
 /* enable != 0: every launch made by qx_contract on this plan is bracketed by a
  * pair of HIP events recorded on the launch's stream. */
 qx_status qx_plan_set_timing(qx_plan *plan, int32_t enable);
@@ -261,10 +284,11 @@ qx_status qx_permute_c64(const void *d_in, void *d_out, int32_t rank, const int3
  * elements.  precision: qx_precision.  M, N, K >= 1.  tile: 0 = a default
  * work-group tile by shape, t + 1 = qx_gemm_tile t (any tile is valid for any
  * M, N).  Asynchronous on stream.
- * QX_SPLIT_BF16 first splits A and B into stream-ordered temporaries
- * (hipMallocAsync, 8*batch*(M+N)*roundup(K,16) bytes, freed on the stream);
- * the split-BF16 products of a plan read operands their producers stored
- * split and allocate nothing.  Errors: QX_ERR_INVALID_ARG (NULL pointer,
+ * The split precisions first split A and B into stream-ordered temporaries
+ * (hipMallocAsync, 8*batch*(M+N)*roundup(K,16) bytes, freed on the stream;
+ * FP16 planes at unit scale, so A and B should lie within FP16's range: values
+ * of magnitude 2^-3 .. 2^15 keep 22 significant bits); the split products of a
+ * plan read operands their producers stored split and allocate nothing.  Errors: QX_ERR_INVALID_ARG (NULL pointer,
  * sizes, strides, tile), QX_ERR_HIP (launch or allocation failure).
  */
 qx_status qx_cgemm(const void *d_a, const void *d_b, void *d_c, int64_t M, int64_t N, int64_t K,
@@ -275,12 +299,12 @@ qx_status qx_cgemm(const void *d_a, const void *d_b, void *d_c, int64_t M, int64
 /*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid hipMalloc): the product of
- * qx_cgemm, same arguments and same kernels, allocating nothing.  The
- * split-BF16 operand copies that qx_cgemm puts in stream-ordered allocations
- * go to a scratch array compiled into the library instead: each device the
- * library runs on holds QX_CGEMM_NOALLOC_SCRATCH_BYTES of it until the process
- * ends.  QX_C64 and QX_SPLIT_FP16 use no scratch.
- *   Limit: with QX_SPLIT_BF16, 8 * batch * (M + N) * roundup(K, 16) bytes must
+ * qx_cgemm, same arguments and same kernels, allocating nothing.  The split
+ * operand copies that qx_cgemm puts in stream-ordered allocations go to a
+ * scratch array compiled into the library instead: each device the library
+ * runs on holds QX_CGEMM_NOALLOC_SCRATCH_BYTES of it until the process ends.
+ * QX_C64 uses no scratch.
+ *   Limit: with a split precision, 8 * batch * (M + N) * roundup(K, 16) bytes must
  *   not exceed QX_CGEMM_NOALLOC_SCRATCH_BYTES, else QX_ERR_INVALID_ARG before
  *   anything is enqueued.
  *   Sharing: every call on a device uses that device's one scratch, which keeps

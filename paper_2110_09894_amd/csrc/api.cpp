@@ -101,17 +101,26 @@ static const int64_t* gather_ptr(qx_plan* p, int g) {
 
 static float* scale_ptr(qx_plan* p, int slot) { return slot < 0 ? nullptr : p->d_misc + 64 + ABSMAX_PARTIALS + slot; }
 
+// Split FP16 tensors are stored as x * 2^(FP16_TARGET_EXP - e) with max |x| < 2^e measured in the
+// calibration pass: the largest value lands below 2^6, leaving FP16's range (65504) a factor of about
+// 1000 of headroom, while values down to 2^-3 keep 22 significant bits and smaller ones an absolute
+// error of at most 2^-25, i.e. 2^-30 of the tensor's largest value.
+constexpr int FP16_TARGET_EXP = 6;
+
 static void resolve_pointers(qx_plan* p) {
   for (Op& op : p->pc.ops) {
     QxCplx* a = op.in_a >= 0 ? tensor_ptr(p, op.in_a) : nullptr;
     QxCplx* b = op.in_b >= 0 ? tensor_ptr(p, op.in_b) : nullptr;
     QxCplx* c = op.out >= 0 ? tensor_ptr(p, op.out) : nullptr;
+    // split FP16 output: the producer applies the output tensor's scale
+    const float* cs = op.out >= 0 ? scale_ptr(p, p->pc.tensors[op.out].scale_slot) : nullptr;
     switch (op.kind) {
       case OP_SIMT:
         op.simt.a = a; op.simt.b = b; op.simt.c = c;
         op.simt.a_gather = gather_ptr(p, op.gather_a);
         op.simt.b_gather = gather_ptr(p, op.gather_b);
         op.simt.block = (op.fix_a.empty() && op.fix_b.empty()) ? nullptr : p->d_state;
+        op.simt.c_scale = cs;
         op.simt.nfix_a = (int)op.fix_a.size();
         op.simt.nfix_b = (int)op.fix_b.size();
         for (size_t i = 0; i < op.fix_a.size(); ++i) {
@@ -129,17 +138,20 @@ static void resolve_pointers(qx_plan* p) {
         op.gemm.b_gather = gather_ptr(p, op.gather_b);
         op.gemm.a_scale = scale_ptr(p, op.scale_slot);
         op.gemm.b_scale = op.scale_slot >= 0 ? scale_ptr(p, op.scale_slot + 1) : nullptr;
+        op.gemm.c_scale = cs;
         break;
       case OP_ABSMAX:
         op.absmax.x = a;
         op.absmax.ticket = reinterpret_cast<unsigned int*>(p->d_misc);
         op.absmax.partial = p->d_misc + 64;
         op.absmax.scale = scale_ptr(p, op.scale_slot);
+        op.absmax.target_exp = FP16_TARGET_EXP;
         break;
       case OP_DOT:
         op.dot.a = a; op.dot.b = b; op.dot.c = c;
         op.dot.a_gather = gather_ptr(p, op.gather_a);
         op.dot.b_gather = gather_ptr(p, op.gather_b);
+        op.dot.c_scale = cs;
         break;
       case OP_PERM:
         op.perm.in = a; op.perm.out = c;
@@ -182,9 +194,17 @@ static int op_class(int kind) {
   }
 }
 
+// How run_op launches an op.  RUN: the plan's own kernels; magnitude reductions
+// are skipped.  CALIBRATE (split FP16 plans, at creation): every tensor is kept
+// in complex64 and the products run on the complex64 kernel, so the magnitude
+// reductions see the values the split FP16 tensors will hold.
+enum RunMode { MODE_RUN = 0, MODE_CALIBRATE = 1 };
+
 // Fixed sliced indices only occur on leaf operands of small contractions,
 // whose kernel adds them from the device-side block state.
-static qx_status run_op(qx_plan* p, const Op& op, int B, hipStream_t s) {
+static qx_status run_op(qx_plan* p, const Op& op, int B, hipStream_t s, int mode = MODE_RUN) {
+  if (op.kind == OP_ABSMAX && mode != MODE_CALIBRATE) return QX_OK;
+  const bool cal = mode == MODE_CALIBRATE;
   const bool outb = op.out >= 0 ? p->pc.tensors[op.out].batched : false;
   const double scale = outb ? (double)B / p->pc.max_b : 1.0;
   hipError_t e = timed(p, op_class(op.kind), op.flops * scale, op.bytes * scale, s, [&]() -> hipError_t {
@@ -192,16 +212,23 @@ static qx_status run_op(qx_plan* p, const Op& op, int B, hipStream_t s) {
     case OP_SIMT: {
       SimtArgs a = op.simt;
       if (outb) a.n_items = B;
+      if (cal) a.c_split = 0;
       return launch_simt(a, s);
     }
     case OP_GEMM: {
       GemmArgs g = op.gemm;
       if (outb) g.n_items = B;
+      if (cal) {
+        g.a_split = g.b_split = g.c_split = 0;
+        g.a_scale = g.b_scale = g.c_scale = nullptr;
+        return launch_gemm(g, QX_C64, op.tile, s);
+      }
       return launch_gemm(g, p->pc.precision, op.tile, s);
     }
     case OP_DOT: {
       DotArgs d = op.dot;
       if (outb) d.n_items = B;
+      if (cal) d.c_split = 0;
       return launch_dot(d, s);
     }
     case OP_ABSMAX: {
@@ -222,17 +249,24 @@ static qx_status run_op(qx_plan* p, const Op& op, int B, hipStream_t s) {
   return QX_OK;
 }
 
-// Estimated seconds for a whole slice range: matrix-core work, plus a launch cost per op.
+// Estimated seconds for a whole slice range: matrix-core work, plus a launch cost per op
+// (magnitude reductions only run at plan creation).
 static double est_cost(const PlanCore& pc) {
   const double blocks = std::ldexp(1.0, pc.n_sliced - pc.js);
   const double flops = pc.flops_block * blocks + pc.flops_call;
-  return flops / 60e12 + blocks * (pc.n_block + 1) * 6e-6 + pc.n_call * 6e-6;
+  int n_block = 0, n_call = 0;
+  for (const Op& o : pc.ops)
+    if (o.kind != OP_ABSMAX) {
+      if (o.phase == PH_BLOCK) ++n_block;
+      else if (o.phase == PH_CALL) ++n_call;
+    }
+  return flops / 60e12 + blocks * (n_block + 1) * 6e-6 + n_call * 6e-6;
 }
 
 // One slice block: take the next block, run the block ops, add its slices'
 // values into the plan's FP64 accumulator.  Reads the block from device state
 // only, so the same launches can be captured once and replayed per block.
-static qx_status run_block(qx_plan* p, int B, hipStream_t s) {
+static qx_status run_block(qx_plan* p, int B, hipStream_t s, int mode = MODE_RUN) {
   const PlanCore& pc = p->pc;
   BlockArgs ba;
   std::memset(&ba, 0, sizeof(ba));
@@ -242,7 +276,7 @@ static qx_status run_block(qx_plan* p, int B, hipStream_t s) {
   hipError_t e = timed(p, QX_OPCLASS_SLICESUM, 0.0, 0.0, s, [&] { return launch_block_advance(ba, s); });
   if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("block advance launch: ") + hipGetErrorString(e));
   for (int i = pc.n_const + pc.n_call; i < (int)pc.ops.size(); ++i) {
-    qx_status r = run_op(p, pc.ops[i], B, s);
+    qx_status r = run_op(p, pc.ops[i], B, s, mode);
     if (r != QX_OK) return r;
   }
   const Tensor& rt = pc.tensors[pc.root];
@@ -261,6 +295,45 @@ static qx_status run_block(qx_plan* p, int B, hipStream_t s) {
   const double sbytes = (8.0 * std::ldexp(1.0, pc.js) + 32.0) * ((int64_t)B << pc.n_open);
   e = timed(p, QX_OPCLASS_SLICESUM, 0.0, sbytes, s, [&] { return launch_slice_sum(sa, s); });
   if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("slice-sum launch: ") + hipGetErrorString(e));
+  return QX_OK;
+}
+
+// Split FP16 plans: fixes every split tensor's power-of-two scale from one
+// complex64 pass (plan-time ops, per-call ops with every bitstring zero, the
+// first slice block), then rewrites the split leaves in split FP16 form and
+// recomputes the plan-time ops in it.  Later calls reuse the scales: a value
+// more than about 1000 times the calibration pass's largest of its tensor would
+// overflow FP16 and make the amplitudes it reaches non-finite.
+static qx_status calibrate_fp16(qx_plan* p, hipStream_t s, int64_t gather_bytes) {
+  const PlanCore& pc = p->pc;
+  for (int i = 0; i < pc.n_const; ++i) {
+    const qx_status r = run_op(p, pc.ops[i], 1, s, MODE_CALIBRATE);
+    if (r != QX_OK) return r;
+  }
+  HIP_TRY(hipMemsetAsync(p->d_gather, 0, gather_bytes, s));
+  BlockArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.state = p->d_state;
+  ba.acc = reinterpret_cast<double*>(p->d_state + 8);
+  ba.slice_end = (int64_t)1 << pc.js;
+  ba.js = pc.js;
+  ba.n_items = pc.max_b << pc.n_open;
+  HIP_TRY(launch_block_init(ba, s));
+  for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
+    const qx_status r = run_op(p, pc.ops[i], pc.max_b, s, MODE_CALIBRATE);
+    if (r != QX_OK) return r;
+  }
+  qx_status r = run_block(p, pc.max_b, s, MODE_CALIBRATE);
+  if (r != QX_OK) return r;
+  for (const Tensor& t : pc.tensors)
+    if (t.is_leaf && t.split) {
+      SplitInplaceArgs a{p->d_leaves + t.leaf_off, t.elems(), scale_ptr(p, t.scale_slot)};
+      HIP_TRY(launch_split_inplace(a, s));
+    }
+  for (int i = 0; i < pc.n_const; ++i) {
+    r = run_op(p, pc.ops[i], 1, s);
+    if (r != QX_OK) return r;
+  }
   return QX_OK;
 }
 
@@ -486,7 +559,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
     std::vector<float> h(2 * p->pc.leaf_pool_elems);
     for (size_t i = 0; i < h.size(); ++i) h[i] = (float)p->pc.leaf_data[i];
     for (const Tensor& t : p->pc.tensors) {
-      if (!t.is_leaf || !t.split) continue;
+      if (!t.is_leaf || !t.split || p->pc.precision != QX_SPLIT_BF16) continue;
       const int64_t E = t.elems();
       std::vector<uint16_t> planes(4 * E);
       for (int64_t e = 0; e < E; ++e) {
@@ -503,11 +576,19 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
         hipSuccess)
       return cleanup(QX_ERR_HIP, std::string("hipMemcpyAsync(leaves): ") + hipGetErrorString(e));
     resolve_pointers(p);
-    for (int i = 0; i < p->pc.n_const; ++i) {
-      qx_status r = run_op(p, p->pc.ops[i], 1, s);
+    if (p->pc.precision == QX_SPLIT_FP16) {
+      qx_status r = calibrate_fp16(p, s, gb);
       if (r != QX_OK) {
         std::string m = g_err;
         return cleanup(r, m);
+      }
+    } else {
+      for (int i = 0; i < p->pc.n_const; ++i) {
+        qx_status r = run_op(p, p->pc.ops[i], 1, s);
+        if (r != QX_OK) {
+          std::string m = g_err;
+          return cleanup(r, m);
+        }
       }
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
@@ -550,6 +631,46 @@ qx_status qx_plan_get_info(const qx_plan* p, qx_plan_info* info) {
   info->flops_call = pc.flops_call;
   info->n_open = pc.n_open;
   info->reserved = 0;
+  return QX_OK;
+}
+
+qx_status qx_plan_get_op_info(const qx_plan* p, int32_t index, qx_op_info* info) {
+  g_err.clear();
+  if (!p || !info) return fail(QX_ERR_INVALID_ARG, "NULL argument");
+  if (index < 0 || index >= (int32_t)p->pc.ops.size()) return fail(QX_ERR_INVALID_ARG, "op index out of range");
+  const Op& op = p->pc.ops[index];
+  std::memset(info, 0, sizeof(*info));
+  info->phase = op.phase;
+  info->op_class = op_class(op.kind);
+  info->tile = -1;
+  info->flops = op.flops;
+  info->bytes = op.bytes;
+  info->batched = op.out >= 0 && p->pc.tensors[op.out].batched ? 1 : 0;
+  switch (op.kind) {
+    case OP_GEMM:
+      info->M = op.gemm.M; info->N = op.gemm.N; info->K = op.gemm.K;
+      info->batch = (int64_t)op.gemm.n_items << op.gemm.nh;
+      info->tile = op.tile;
+      break;
+    case OP_SIMT:
+      info->M = (int64_t)1 << op.simt.n_out; info->N = 1; info->K = (int64_t)1 << op.simt.n_k;
+      info->batch = op.simt.n_items;
+      break;
+    case OP_DOT:
+      info->M = (int64_t)1 << op.dot.n_out; info->N = 1; info->K = op.dot.K;
+      info->batch = op.dot.n_items;
+      break;
+    case OP_PERM:
+      info->M = (int64_t)1 << op.perm.rank; info->N = 1; info->K = 1;
+      info->batch = op.perm.n_items;
+      break;
+    default: {
+      const Tensor& t = p->pc.tensors[op.in_a];
+      info->M = t.elems(); info->N = 1; info->K = 1;
+      info->batch = t.batched ? p->pc.max_b : 1;
+      info->batched = t.batched ? 1 : 0;
+    }
+  }
   return QX_OK;
 }
 
@@ -771,7 +892,7 @@ qx_status qx_permute_c64(const void* d_in, void* d_out, int32_t rank, const int3
   return QX_OK;
 }
 
-// Shared by qx_cgemm and qx_cgemm_noalloc.  Split BF16 splits A and B into
+// Shared by qx_cgemm and qx_cgemm_noalloc.  Split precision splits A and B into
 // temporaries first: in `scratch` when given (it holds at least
 // cgemm_split_bytes(...) bytes), else in stream-ordered allocations.
 static int64_t cgemm_split_bytes(int64_t M, int64_t N, int64_t K, int64_t batch) {
@@ -811,13 +932,14 @@ static qx_status cgemm_run(const void* d_a, const void* d_b, void* d_c, int64_t 
   g.vec_a = a_ks == 1 && a_ms % 2 == 0 && stride_a % 2 == 0 && ((uintptr_t)d_a) % 16 == 0;
   g.vec_b = b_ks == 1 && b_ns % 2 == 0 && stride_b % 2 == 0 && ((uintptr_t)d_b) % 16 == 0;
   const int tile = tile_opt > 0 ? tile_opt - 1 : gemm_default_tile(M, N);
-  if (precision != QX_SPLIT_BF16) {
+  if (precision == QX_C64) {
     gemm_args_setup(g);
     HIP_TRY(launch_gemm(g, precision, tile, s));
     return QX_OK;
   }
-  // split BF16: the product reads pre-split operands, so split A and B into
-  // temporaries [item][row][kp] (k zero-padded to a multiple of 16) first
+  // split precision: the product reads pre-split operands, so split A and B into
+  // temporaries [item][row][kp] (k zero-padded to a multiple of 16) first; FP16
+  // planes at unit scale
   const int64_t kp = (K + 15) / 16 * 16;
   const int64_t pa = batch * M * kp, pb = batch * N * kp;
   uint16_t *ta = scratch, *tb = scratch ? scratch + 4 * pa : nullptr;
@@ -829,8 +951,9 @@ static qx_status cgemm_run(const void* d_a, const void* d_b, void* d_c, int64_t 
       return fail(QX_ERR_HIP, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
   }
-  SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, (int32_t)batch};
-  SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, (int32_t)batch};
+  const int32_t kind = precision == QX_SPLIT_FP16 ? 2 : 1;
+  SplitPlanesArgs sa{(const QxCplx*)d_a, ta, M, K, kp, a_ms, a_ks, stride_a, (int32_t)batch, kind};
+  SplitPlanesArgs sb{(const QxCplx*)d_b, tb, N, K, kp, b_ns, b_ks, stride_b, (int32_t)batch, kind};
   hipError_t e = launch_split_planes(sa, s);
   if (e == hipSuccess) e = launch_split_planes(sb, s);
   if (e == hipSuccess) {
@@ -848,13 +971,13 @@ static qx_status cgemm_run(const void* d_a, const void* d_b, void* d_c, int64_t 
     hipFreeAsync(ta, s);
     hipFreeAsync(tb, s);
   }
-  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("split-BF16 product: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("split product: ") + hipGetErrorString(e));
   return QX_OK;
 }
 
 }  // extern "C"
 
-// Scratch of qx_cgemm_noalloc: the split-BF16 operand copies of one call.  Every
+// Scratch of qx_cgemm_noalloc: the split operand copies of one call.  Every
 // device the library runs on holds its own instance until the process ends.  Host
 // code must not pass this name to a kernel (on the host it is only a stand-in
 // for the symbol): the device address comes from hipGetSymbolAddress, per device.
@@ -891,10 +1014,10 @@ qx_status qx_cgemm_noalloc(const void* d_a, const void* d_b, void* d_c, int64_t 
   const qx_status st = cgemm_check(d_a, d_b, d_c, M, N, K, a_ms, a_ks, b_ks, b_ns, batch, precision, tile_opt);
   if (st != QX_OK) return st;
   uint16_t* scr = nullptr;
-  if (precision == QX_SPLIT_BF16 && batch > 0) {
+  if (precision != QX_C64 && batch > 0) {
     const double need = 8.0 * (double)batch * ((double)M + (double)N) * (double)((K + 15) / 16 * 16);
     if (need > (double)QX_CGEMM_NOALLOC_SCRATCH_BYTES)
-      return fail(QX_ERR_INVALID_ARG, "split-BF16 operand copies need " + std::to_string((int64_t)need) +
+      return fail(QX_ERR_INVALID_ARG, "split operand copies need " + std::to_string((int64_t)need) +
                                           " bytes; the allocation-free product's scratch holds " +
                                           std::to_string((int64_t)QX_CGEMM_NOALLOC_SCRATCH_BYTES));
     const qx_status sst = noalloc_scratch(&scr);

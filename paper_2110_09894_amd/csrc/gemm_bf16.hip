@@ -1,11 +1,13 @@
-// Split-precision complex GEMM on BF16 matrix cores with pre-split operands.
+// Split-precision complex GEMM on BF16 or FP16 matrix cores with pre-split operands.
 //
 // Both operands are stored split (split_format.h: 64-byte chunks of 8 elements
 // holding hi re, lo re, hi im, lo im), so the k loop converts nothing:
 //   A B ~= Ah Bh + Ah Bl + Al Bh
-// per real product, accumulated in FP32 by v_mfma_f32_32x32x16_bf16, with the
-// complex product as four real ones (the sign of Im A Im B is applied by
-// flipping the sign bits of the Im A fragments).
+// per real product, accumulated in FP32 by v_mfma_f32_32x32x16_bf16 (or _f16),
+// with the complex product as four real ones (the sign of Im A Im B is applied
+// by flipping the sign bits of the Im A fragments).  FP16 operands hold the
+// values times their tensors' power-of-two scales; the epilogue divides them
+// out (and applies the output's own scale when it is stored split FP16).
 //
 // Staging.  A tile is ROWS rows x 16 k; in LDS a row is 128 bytes = eight
 // 16-byte slots, one per (k half g, plane q), and slot (g, q) of row r sits at
@@ -26,6 +28,7 @@ namespace qx {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -132,10 +135,15 @@ struct RegTile {
 __device__ __forceinline__ v16f mfma(bf16x8 a, bf16x8 b, v16f c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ bf16x8 neg(bf16x8 x) {
+__device__ __forceinline__ v16f mfma(f16x8 a, f16x8 b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+// sign flip of all 8 values (BF16 and FP16 both keep the sign in bit 15)
+template <class T>
+__device__ __forceinline__ T neg(T x) {
   u32x4 t = __builtin_bit_cast(u32x4, x);
   t ^= 0x80008000u;
-  return __builtin_bit_cast(bf16x8, t);
+  return __builtin_bit_cast(T, t);
 }
 
 // s_waitcnt for "at most n vector-memory operations outstanding" (expcnt and
@@ -167,9 +175,9 @@ __device__ __forceinline__ void stage_barrier() {
 // BM x BN work-group tile computed by WGM x WGN waves; NS LDS stages.  Each
 // wave takes its fragments of k tile t into registers before tile t is
 // multiplied, so the copies of tiles t + 1 .. t + NS are in flight meanwhile.
-template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
-__global__ __launch_bounds__(64 * WGM * WGN, (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024) ? 2 : 1)
-void k_gemm_bf16s(GemmArgs p) {
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool F16>
+__device__ __forceinline__ void gemm_split16(const GemmArgs& p) {
+  using frag = typename std::conditional<F16, f16x8, bf16x8>::type;
   constexpr int NW = WGM * WGN, NT = 64 * NW;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 32, FN = WN / 32;
@@ -281,22 +289,22 @@ void k_gemm_bf16s(GemmArgs p) {
     const bool more = kt + NS < nk;
     const char* bufA = smem + BI * BUF;
     const char* bufB = bufA + ABYTES;
-    bf16x8 arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
+    frag arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
       const char* r = bufA + (wm * WM + a * 32) * 128;
-      arh[a] = *(const bf16x8*)(r + fo[0]);
-      arl[a] = *(const bf16x8*)(r + fo[1]);
-      aih[a] = *(const bf16x8*)(r + fo[2]);
-      ail[a] = *(const bf16x8*)(r + fo[3]);
+      arh[a] = *(const frag*)(r + fo[0]);
+      arl[a] = *(const frag*)(r + fo[1]);
+      aih[a] = *(const frag*)(r + fo[2]);
+      ail[a] = *(const frag*)(r + fo[3]);
     }
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
       const char* r = bufB + (wn * WN + b * 32) * 128;
-      brh[b] = *(const bf16x8*)(r + fo[0]);
-      brl[b] = *(const bf16x8*)(r + fo[1]);
-      bih[b] = *(const bf16x8*)(r + fo[2]);
-      bil[b] = *(const bf16x8*)(r + fo[3]);
+      brh[b] = *(const frag*)(r + fo[0]);
+      brl[b] = *(const frag*)(r + fo[1]);
+      bih[b] = *(const frag*)(r + fo[2]);
+      bil[b] = *(const frag*)(r + fo[3]);
     }
     stage_barrier();
     if (more) {
@@ -381,11 +389,33 @@ void k_gemm_bf16s(GemmArgs p) {
     if (kt + 2 < nk) step(kt + 2, Int<2>{});
 
   const OutMap om = out_map(p, m0, n0);
-  store_blocks<FM, FN, WM, WN, true>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, 1.f,
-                                     reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
+  // FP16: divide out the operands' scales, apply the output's when it is stored split (powers of two: exact)
+  const float f = F16 ? (p.c_split ? out_scale(p.c_scale) : 1.f) / (out_scale(p.a_scale) * out_scale(p.b_scale))
+                      : 1.f;
+  store_blocks<FM, FN, WM, WN, true, F16 ? 2 : 1>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, f,
+                                                 reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
 }
 
-template <int BM, int BN, int WGM, int WGN, int NS>
+// Two wavefronts per SIMD where the LDS stages allow two work-groups per CU.
+#define QX_SPLIT16_BOUNDS \
+  __launch_bounds__(64 * WGM * WGN, (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024) ? 2 : 1)
+
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
+__global__ QX_SPLIT16_BOUNDS void k_gemm_bf16s(GemmArgs p) {
+  gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, false>(p);
+}
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
+__global__ QX_SPLIT16_BOUNDS void k_gemm_fp16s(GemmArgs p) {
+  gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, true>(p);
+}
+
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool F16>
+static void launch_kernel(dim3 grid, dim3 block, hipStream_t s, const GemmArgs& a) {
+  if constexpr (F16) hipLaunchKernelGGL((k_gemm_fp16s<BM, BN, WGM, WGN, NS, A_KC, B_KC>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, A_KC, B_KC>), grid, block, 0, s, a);
+}
+
+template <int BM, int BN, int WGM, int WGN, int NS, bool F16>
 static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
@@ -393,25 +423,28 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool akc = gemm_a_kc(a), bkc = gemm_b_kc(a);
   dim3 grid((unsigned)nwg), block(64 * WGM * WGN);
-  if (akc && bkc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, true, true>), grid, block, 0, s, a);
-  else if (akc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, true, false>), grid, block, 0, s, a);
-  else if (bkc) hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, false, false>), grid, block, 0, s, a);
+  if (akc && bkc) launch_kernel<BM, BN, WGM, WGN, NS, true, true, F16>(grid, block, s, a);
+  else if (akc) launch_kernel<BM, BN, WGM, WGN, NS, true, false, F16>(grid, block, s, a);
+  else if (bkc) launch_kernel<BM, BN, WGM, WGN, NS, false, true, F16>(grid, block, s, a);
+  else launch_kernel<BM, BN, WGM, WGN, NS, false, false, F16>(grid, block, s, a);
   return hipGetLastError();
 }
 
-
-hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) {
+template <bool F16>
+static hipError_t launch_split16(const GemmArgs& a, int tile, hipStream_t s) {
   // operands must be stored split, and K a multiple of the 16-wide k tile (or 8: one half tile)
   if (!a.a_split || !a.b_split || (a.K % 16 != 0 && a.K != 8)) return hipErrorInvalidValue;
   switch (tile) {
-    case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2>(a, s);
-    case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3>(a, s);
-    case GEMM_TILE_64x128: return launch_bf16s<64, 128, 2, 2, 3>(a, s);
-    case GEMM_TILE_256x128: return launch_bf16s<256, 128, 4, 2, 3>(a, s);
-    case GEMM_TILE_128x256: return launch_bf16s<128, 256, 2, 4, 3>(a, s);
-    default: return launch_bf16s<128, 128, 2, 2, 2>(a, s);
+    case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2, F16>(a, s);
+    case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3, F16>(a, s);
+    case GEMM_TILE_64x128: return launch_bf16s<64, 128, 2, 2, 3, F16>(a, s);
+    case GEMM_TILE_256x128: return launch_bf16s<256, 128, 4, 2, 3, F16>(a, s);
+    case GEMM_TILE_128x256: return launch_bf16s<128, 256, 2, 4, 3, F16>(a, s);
+    default: return launch_bf16s<128, 128, 2, 2, 2, F16>(a, s);
   }
 }
+
+hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s) { return launch_split16<false>(a, tile, s); }
+hipError_t launch_gemm_fp16(const GemmArgs& a, int tile, hipStream_t s) { return launch_split16<true>(a, tile, s); }
 
 }  // namespace qx

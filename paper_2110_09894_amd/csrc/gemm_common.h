@@ -230,7 +230,16 @@ __device__ __forceinline__ void wave_lds_fence() {
 // work-group barrier after the last LDS read of the k loop, so the stage areas
 // (which alias the operand buffers) are free; afterwards each wave only touches
 // its own area.
-template <int FM, int FN, int WM, int WN, bool UNROLL>
+// Planes of a value already multiplied by the output's scale factor: BF16 (KIND 1) or FP16 (KIND 2).
+template <int KIND>
+__device__ __forceinline__ void split_scaled(QxCplx v, uint32_t& hi, uint32_t& lo) {
+  if constexpr (KIND == 2) split_pair_f16(v, hi, lo);
+  else split_pair(v, hi, lo);
+}
+
+// scale multiplies every accumulator before it is stored (split FP16: the output's scale over the
+// operands'); KIND is the split storage written when p.c_split is set.
+template <int FM, int FN, int WM, int WN, bool UNROLL, int KIND = 1>
 __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMap& om, int64_t m0,
                                     int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
                                     const v16f (&ci)[FM][FN], float scale, QxCplx* stage) {
@@ -253,8 +262,9 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
 #pragma unroll
           for (int d = 0; d < 4; ++d) {
             uint32_t hi0, lo0, hi1, lo1, w[4];
-            split_pair(QxCplx{cr[a][b][8 * j + 2 * d] * scale, ci[a][b][8 * j + 2 * d] * scale}, hi0, lo0);
-            split_pair(QxCplx{cr[a][b][8 * j + 2 * d + 1] * scale, ci[a][b][8 * j + 2 * d + 1] * scale}, hi1, lo1);
+            split_scaled<KIND>(QxCplx{cr[a][b][8 * j + 2 * d] * scale, ci[a][b][8 * j + 2 * d] * scale}, hi0, lo0);
+            split_scaled<KIND>(QxCplx{cr[a][b][8 * j + 2 * d + 1] * scale, ci[a][b][8 * j + 2 * d + 1] * scale}, hi1,
+                               lo1);
             split_words(hi0, lo0, hi1, lo1, w);
 #pragma unroll
             for (int q = 0; q < 4; ++q) pl[q][d] = w[q];
@@ -324,8 +334,8 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
 #pragma unroll
           for (int d = 0; d < 4; ++d) {
             uint32_t hi0, lo0, hi1, lo1, w[4];
-            split_pair(stage[ck.sidx[s][2 * d]], hi0, lo0);
-            split_pair(stage[ck.sidx[s][2 * d + 1]], hi1, lo1);
+            split_scaled<KIND>(stage[ck.sidx[s][2 * d]], hi0, lo0);
+            split_scaled<KIND>(stage[ck.sidx[s][2 * d + 1]], hi1, lo1);
             split_words(hi0, lo0, hi1, lo1, w);
 #pragma unroll
             for (int q = 0; q < 4; ++q) pl[q][d] = w[q];
@@ -339,7 +349,7 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const int lmi = ck.sidx[s][i] / 33, lni = ck.sidx[s][i] % 33;
-              if (m0 + lm0 + lmi < p.M && n0 + ln0 + lni < p.N) store_split(C16, e0 + i, stage[ck.sidx[s][i]]);
+              if (m0 + lm0 + lmi < p.M && n0 + ln0 + lni < p.N) store_split(C16, e0 + i, stage[ck.sidx[s][i]], KIND);
             }
           }
         }
@@ -358,7 +368,7 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
           }
         if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) {
           const QxCplx v = stage[lm * 33 + ln];
-          if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), eb + off, v);
+          if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), eb + off, v, KIND);
           else p.c[eb + off] = v;
         }
       };

@@ -36,7 +36,8 @@ struct SimtArgs {
   const int64_t *a_gather, *b_gather;    // per-item offsets, or null
   int32_t n_out, n_k, n_items;
   int32_t pad_;
-  int32_t c_split, pad2_;                // C is stored in split BF16 form
+  int32_t c_split, pad2_;                // C's storage: 0 complex64, 1 split BF16, 2 split FP16 of C * *c_scale
+  const float *c_scale;                  // split FP16: C's power-of-two scale
   int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];   // strides of output bit i (0 if absent)
   int64_t a_ks[QX_MAX_KBITS], b_ks[QX_MAX_KBITS]; // strides of contracted bit j
 };
@@ -50,8 +51,10 @@ struct SimtArgs {
 //   A(m, k) at sum_i bit_i(m) a_rs[i] + sum_j bit_j(k) a_kst[j], etc.
 // a_kc / b_kc: k bits 0..2 are unit-stride-contiguous (8 consecutive k values
 // are 8 consecutive elements), which enables 16-byte loads along k.
-// a_split / b_split / c_split: the operand is stored in split BF16 form
-// (split-BF16 products), else complex64.
+// a_split / b_split: the operand is stored split (split_format.h: BF16 planes,
+// or FP16 planes of the value times the tensor's power-of-two scale *a_scale /
+// *b_scale); c_split: C's storage, 0 complex64, 1 split BF16, 2 split FP16 of
+// C * *c_scale.
 #define QX_GEMM_BITS 32
 struct GemmArgs {
   const QxCplx *a, *b;
@@ -62,7 +65,7 @@ struct GemmArgs {
   const int64_t *a_gather, *b_gather;
   int32_t n_items, nh;                   // nh = number of shared-slice bits
   int32_t vec_a, vec_b;                  // 16-byte vector loads allowed along k (alignment)
-  const float *a_scale, *b_scale;        // split FP16: power-of-two operand scales (null = 1)
+  const float *a_scale, *b_scale, *c_scale;  // split FP16: power-of-two tensor scales (null = 1)
   int32_t bits, nm, nn, nk;              // bit-scattered mode and log2 of M, N, K
   int32_t a_kc, b_kc;
   int32_t a_split, b_split, c_split, pad_split_;
@@ -90,7 +93,8 @@ struct DotArgs {
   int64_t a_item, b_item, c_item;
   const int64_t *a_gather, *b_gather;
   int32_t n_out, n_items;
-  int32_t c_split, pad2_;                // C is stored in split BF16 form
+  int32_t c_split, pad2_;                // C's storage: 0 complex64, 1 split BF16, 2 split FP16 of C * *c_scale
+  const float *c_scale;
   int64_t a_os[QX_MAX_BITS], b_os[QX_MAX_BITS];
 };
 
@@ -125,8 +129,8 @@ struct SliceSumArgs {
   int64_t o_stride[QX_MAX_OBITS];
 };
 
-// Largest magnitude of a tensor -> power-of-two scale for FP16 operands:
-//   scale[0] = 2^(14 - e) with max |re|, |im| < 2^e   (1 if the tensor is zero)
+// Largest magnitude of a tensor -> power-of-two scale for FP16 storage:
+//   scale[0] = 2^(target_exp - e) with max |re|, |im| < 2^e   (1 if the tensor is zero)
 // Work-groups write partial maxima; the last one to finish (ticket counter)
 // reduces them, writes the scale and resets the counter for the next launch.
 struct AbsmaxArgs {
@@ -135,6 +139,7 @@ struct AbsmaxArgs {
   float *partial;                       // [gridDim.x]
   unsigned int *ticket;                 // zero before the first launch; left zero after each
   float *scale;
+  int32_t target_exp, pad_;
 };
 
 // Slice-block state kept on the device so one captured block program can be
@@ -149,13 +154,21 @@ struct BlockArgs {
   int32_t js, n_items;
 };
 
-// Complex64 matrices -> split BF16 form, k padded with zeros to kp:
+// Complex64 matrices -> split form (kind 1 BF16, 2 FP16 at unit scale), k padded with zeros to kp:
 //   out[item][r][k'] (split) = in[item * in_item + r * ld_r + k' * ld_k] for k' < K, else 0
 struct SplitPlanesArgs {
   const QxCplx *in;
   uint16_t *out;
   int64_t rows, K, kp, ld_r, ld_k, in_item;
-  int32_t n_items;
+  int32_t n_items, kind;
+};
+
+// A complex64 tensor of n elements (n a multiple of 8) rewritten in place in split FP16
+// form of x * *scale: every 64-byte chunk of 8 elements becomes their four planes.
+struct SplitInplaceArgs {
+  QxCplx *x;
+  int64_t n;
+  const float *scale;
 };
 
 // Per-bitstring gather offsets: out[item] = sum_j bit_{q_j}(x[item]) * stride_j

@@ -26,8 +26,8 @@ int gemm_default_tile(int64_t M, int64_t N);
 hipError_t launch_simt(const SimtArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, int precision, int tile, hipStream_t s);
 hipError_t launch_gemm_c64(const GemmArgs& a, int tile, hipStream_t s);
-hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s);  // operands stored split
-hipError_t launch_gemm_fp16(const GemmArgs& a, int tile, hipStream_t s);
+hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s);  // operands stored split BF16
+hipError_t launch_gemm_fp16(const GemmArgs& a, int tile, hipStream_t s);  // operands stored split FP16
 hipError_t launch_dot(const DotArgs& a, hipStream_t s);
 void permute_setup(PermArgs& a);  // fills the tile / outer-bit fields from rank and in_pos
 void gemm_args_setup(GemmArgs& g);  // fills the epilogue bit order and the k-tile steps
@@ -35,6 +35,7 @@ hipError_t launch_permute(const PermArgs& a, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_split_planes(const SplitPlanesArgs& a, hipStream_t s);
+hipError_t launch_split_inplace(const SplitInplaceArgs& a, hipStream_t s);  // n % 8 == 0
 hipError_t launch_block_init(const BlockArgs& a, hipStream_t s);
 hipError_t launch_block_advance(const BlockArgs& a, hipStream_t s);
 hipError_t launch_block_finish(const BlockArgs& a, double* amp, hipStream_t s);

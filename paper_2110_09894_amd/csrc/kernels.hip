@@ -7,7 +7,7 @@
 //   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)
 // The matrix-core products (Sec. IV-A: contractions mapped to matrix
-// multiplications) are in gemm_f32.hip / gemm_bf16.hip / gemm_fp16.hip.
+// multiplications) are in gemm_f32.hip (complex64) and gemm_bf16.hip (split BF16 / FP16).
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
   const int64_t e = (int64_t)item * p.c_item + o;
   if (chunked) {
     uint32_t hi, lo;
-    split_pair(acc, hi, lo);
+    split_value(p.c_split, out_scale(p.c_scale), acc, hi, lo);
     sp[split_off(tid, 0)] = (uint16_t)hi;
     sp[split_off(tid, 1)] = (uint16_t)lo;
     sp[split_off(tid, 2)] = (uint16_t)(hi >> 16);
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_simt(SimtArgs p) {
     if (tid < 128)
       *(v4u*)(reinterpret_cast<uint16_t*>(p.c) + split_chunk(e - tid) + 8 * tid) = *(const v4u*)(sp + 8 * tid);
   } else if (p.c_split) {
-    store_split(reinterpret_cast<uint16_t*>(p.c), e, acc);
+    store_split(reinterpret_cast<uint16_t*>(p.c), e, acc, p.c_split, out_scale(p.c_scale));
   } else {
     p.c[e] = acc;
   }
@@ -164,7 +164,8 @@ __global__ __launch_bounds__(256) void k_dot(DotArgs p) {
   if (threadIdx.x == 0) {
     QxCplx r = {(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
                 (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
-    if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, r);
+    if (p.c_split)
+      store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, r, p.c_split, out_scale(p.c_scale));
     else p.c[(int64_t)item * p.c_item + o] = r;
   }
 }
@@ -208,7 +209,9 @@ __global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
     acc.y += __shfl_xor(acc.y, off, 64);
   }
   if (sub == 0) {
-    if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc);
+    if (p.c_split)
+      store_split(reinterpret_cast<uint16_t*>(p.c), (int64_t)item * p.c_item + o, acc, p.c_split,
+                  out_scale(p.c_scale));
     else p.c[(int64_t)item * p.c_item + o] = acc;
   }
 }
@@ -221,7 +224,36 @@ __global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
     const int64_t item = e / per, rk = e - item * per;
     const int64_t r = rk / p.kp, k = rk - r * p.kp;
     const QxCplx v = k < p.K ? p.in[item * p.in_item + r * p.ld_r + k * p.ld_k] : QxCplx{0.f, 0.f};
-    store_split(p.out, e, v);
+    store_split(p.out, e, v, p.kind);
+  }
+}
+
+// In-place conversion of a complex64 tensor to split FP16 form (x * scale): a thread reads one
+// 64-byte chunk of 8 elements and writes back their four planes in the same 64 bytes.  (Leaves
+// start at any 8-byte boundary, so the accesses are 8 bytes wide.)
+__global__ __launch_bounds__(256) void k_split_inplace(SplitInplaceArgs p) {
+  const float sc = out_scale(p.scale);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < p.n / 8; c += (int64_t)gridDim.x * blockDim.x) {
+    QxCplx* x = p.x + 8 * c;
+    QxCplx v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = x[j];
+    uint32_t w[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t hi0, lo0, hi1, lo1, q[4];
+      split_value(2, sc, v[2 * j], hi0, lo0);
+      split_value(2, sc, v[2 * j + 1], hi1, lo1);
+      split_words(hi0, lo0, hi1, lo1, q);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) w[pl][j] = q[pl];
+    }
+    uint2* o = reinterpret_cast<uint2*>(x);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      o[2 * pl] = uint2{w[pl][0], w[pl][1]};
+      o[2 * pl + 1] = uint2{w[pl][2], w[pl][3]};
+    }
   }
 }
 
@@ -396,7 +428,7 @@ __global__ __launch_bounds__(256) void k_absmax(AbsmaxArgs p) {
     if (mx > 0.f && mx < 3.0e38f) {
       int e;
       frexpf(mx, &e);  // mx < 2^e
-      int k = 14 - e;
+      int k = p.target_exp - e;
       k = k > 100 ? 100 : (k < -100 ? -100 : k);
       sc = ldexpf(1.f, k);
     }
@@ -606,6 +638,14 @@ hipError_t launch_split_planes(const SplitPlanesArgs& a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t want = (n + 255) / 256;
   hipLaunchKernelGGL(k_split_planes, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_inplace(const SplitInplaceArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.n % 8 != 0) return hipErrorInvalidValue;
+  const int64_t want = (a.n / 8 + 255) / 256;
+  hipLaunchKernelGGL(k_split_inplace, dim3((unsigned)(want < 4096 ? want : 4096)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -97,7 +97,9 @@ struct Compiler {
 
   Compiler(PlanCore& p, std::string& e) : pc(p), err(e) {}
 
-  bool split_bf16() const { return pc.precision == QX_SPLIT_BF16; }
+  // split-precision plans store every matrix-product operand split (BF16 or scaled FP16 planes)
+  bool split() const { return pc.precision == QX_SPLIT_BF16 || pc.precision == QX_SPLIT_FP16; }
+  int split_kind() const { return pc.precision == QX_SPLIT_FP16 ? 2 : 1; }
 
   bool is_fixed(int lab) const { return pc.kind[lab] == KIND_SLICE && pc.aux[lab] >= pc.js; }
   bool is_vary(int lab) const { return pc.kind[lab] == KIND_SLICE && pc.aux[lab] < pc.js; }
@@ -278,8 +280,9 @@ struct Compiler {
         if (pc.kind[lab] == KIND_REG) ++regw;
       pc.width = std::max(pc.width, regw);
     }
-    // split-BF16 plans store every matrix-product operand split; leaves are split at upload
-    if (split_bf16())
+    // split plans store every matrix-product operand split; leaves are split at upload (BF16) or after
+    // the scale calibration at plan creation (FP16)
+    if (split())
       for (int t = 0; t < n; ++t)
         if (nodes[t].parent >= 0 && nodes[nodes[t].parent].cls == CLS_GEMM) pc.tensors[nodes[t].tensor].split = true;
     for (int t = 0; t < n - 1; ++t)
@@ -331,7 +334,7 @@ struct Compiler {
           if (contains(kq, lab)) kord.push_back(lab);
         for (int lab : small.lay)
           if (contains(kq, lab) && std::find(kord.begin(), kord.end(), lab) == kord.end()) kord.push_back(lab);
-        if (!matched && Q.cls == CLS_GEMM && split_bf16())
+        if (!matched && Q.cls == CLS_GEMM && split())
           for (int lab : register_epilogue_lead(p, sib, kord)) push(lab);
         for (int lab : kord) push(lab);
       }
@@ -398,7 +401,7 @@ struct Compiler {
     // straight from the accumulators: that side becomes M, numbered so that m bits 0, 1, 3
     // (the rows one lane holds in its accumulator groups) are those three indices.
     bool ep_reg = false;
-    if (split_bf16() && out.split && out.lay.size() >= 3) {
+    if (split() && out.split && out.lay.size() >= 3) {
       const bool fa = contains(nd.Fa, out.lay[0]) && contains(nd.Fa, out.lay[1]) && contains(nd.Fa, out.lay[2]);
       const bool fb = contains(nd.Fb, out.lay[0]) && contains(nd.Fb, out.lay[1]) && contains(nd.Fb, out.lay[2]);
       if ((fa && nd.Fa.size() >= 4) || (fb && nd.Fb.size() >= 4)) {
@@ -474,7 +477,7 @@ struct Compiler {
     }
     g.a_kc = kca;
     g.b_kc = kcb;
-    if (split_bf16()) {
+    if (split()) {
       if (!XA.split || !XB.split) err = "internal: matrix-product operand not stored split";
       g.a_split = g.b_split = 1;
     }
@@ -495,8 +498,12 @@ struct Compiler {
     g.ep_reg = ep_reg;
     op.kind = OP_GEMM;
     if (pc.precision == QX_SPLIT_FP16) {
+      // each operand's scale slot (a tensor has one consumer); the magnitude reductions that fill
+      // them run only in the calibration pass at plan creation
       op.scale_slot = pc.n_scale_slots;
       pc.n_scale_slots += 2;
+      pc.tensors[tA].scale_slot = op.scale_slot;
+      pc.tensors[tB].scale_slot = op.scale_slot + 1;
       for (int side = 0; side < 2; ++side) {
         const int ti = side == 0 ? tA : tB;
         Op am;
@@ -522,7 +529,7 @@ struct Compiler {
     Tensor out;
     out.batched = nd.batched;
     out.phase = nd.phase;
-    out.split = split_bf16() && nd.parent >= 0 && nodes[nd.parent].cls == CLS_GEMM;
+    out.split = split() && nd.parent >= 0 && nodes[nd.parent].cls == CLS_GEMM;
     Op op;
     op.phase = nd.phase;
     const double items = nd.batched ? pc.max_b : 1;
@@ -624,7 +631,7 @@ struct Compiler {
     op.bytes = 8.0 * ((double)pc.tensors[op.in_a].elems() * ia + (double)pc.tensors[op.in_b].elems() * ib +
                       (double)O.elems() * items);
     const int64_t citem = O.batched ? O.elems() : 0;
-    const int csplit = O.split ? 1 : 0;
+    const int csplit = O.split ? split_kind() : 0;
     if (op.kind == OP_SIMT) { op.simt.c_item = citem; op.simt.c_split = csplit; }
     if (op.kind == OP_GEMM) { op.gemm.c_item = citem; op.gemm.c_split = csplit; }
     if (op.kind == OP_DOT) { op.dot.c_item = citem; op.dot.c_split = csplit; }

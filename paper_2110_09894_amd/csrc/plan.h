@@ -35,7 +35,8 @@ struct Tensor {
   int phase = PH_CONST;
   int64_t arena_off = -1;        // byte offset in the arena (non-leaf)
   int first_op = -1, last_op = -1;
-  bool split = false;            // stored as split BF16 planes (operand of a split-BF16 product)
+  bool split = false;            // stored split (operand of a split-precision product)
+  int scale_slot = -1;           // split FP16: slot of the tensor's power-of-two scale
   int64_t elems() const { return (int64_t)1 << lay.size(); }
 };
 

@@ -28,7 +28,8 @@ QX_SPLIT_BF16 = 1
 QX_SPLIT_FP16 = 2
 PRECISIONS = {"c64": QX_C64, "split_bf16": QX_SPLIT_BF16, "split_fp16": QX_SPLIT_FP16}
 
-EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_plan_peak_bytes", "qx_contract", "qx_plan_destroy",
+EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_plan_get_op_info", "qx_plan_peak_bytes", "qx_contract",
+            "qx_plan_destroy",
             "qx_last_error", "qx_plan_set_timing", "qx_plan_get_timing", "qx_permute_c64", "qx_cgemm",
             "qx_cgemm_noalloc"]
 CGEMM_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -79,6 +80,18 @@ class PlanInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class OpInfo(C.Structure):
+    _fields_ = [("phase", C.c_int32), ("op_class", C.c_int32), ("M", C.c_int64), ("N", C.c_int64),
+                ("K", C.c_int64), ("batch", C.c_int64), ("tile", C.c_int32), ("batched", C.c_int32),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["op_class"] = OPCLASSES[d["op_class"]]
+        d["tile"] = TILES[d["tile"]] if d["tile"] >= 0 else None
+        return d
+
+
 class _OpTiming(C.Structure):
     _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
@@ -97,6 +110,8 @@ def lib():
                                      C.POINTER(_Options), C.c_void_p, C.POINTER(C.c_void_p)]
         L.qx_plan_get_info.restype = C.c_int
         L.qx_plan_get_info.argtypes = [C.c_void_p, C.POINTER(PlanInfo)]
+        L.qx_plan_get_op_info.restype = C.c_int
+        L.qx_plan_get_op_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(OpInfo)]
         L.qx_plan_peak_bytes.restype = C.c_int
         L.qx_plan_peak_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.qx_contract.restype = C.c_int
@@ -184,6 +199,16 @@ class Plan:
         inf = PlanInfo()
         _check(lib().qx_plan_get_info(self.handle, C.byref(inf)))
         return inf.as_dict()
+
+    def ops(self) -> list:
+        """Every device op of the plan in launch order (qx_plan_get_op_info)."""
+        inf = self.info()
+        out = []
+        for i in range(inf["n_ops_const"] + inf["n_ops_call"] + inf["n_ops_block"]):
+            o = OpInfo()
+            _check(lib().qx_plan_get_op_info(self.handle, i, C.byref(o)))
+            out.append(o.as_dict())
+        return out
 
     def peak_bytes(self, n_bitstrings=0, slice_batch_log2=-1) -> int:
         """Device bytes of this plan recompiled for another bitstring capacity / slice batch (host only)."""

@@ -181,7 +181,8 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"qx_plan_options": qxtn._Options, "qx_plan_info": qxtn.PlanInfo, "qx_network": qxtn._Network}
+    structs = {"qx_plan_options": qxtn._Options, "qx_plan_info": qxtn.PlanInfo, "qx_network": qxtn._Network,
+               "qx_op_info": qxtn.OpInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qxtn.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -239,3 +240,24 @@ def test_peak_bytes_matches_compiled_plans_and_is_monotone(cfg):
     _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(-1))
     _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(0, len(sl) + 1))
     _expect(qxtn.QX_ERR_INVALID_ARG, lambda: p.peak_bytes(0, -2))
+
+
+def test_op_info_lists_the_compiled_program():
+    from workloads import configs
+    w = configs.get("c2")
+    tree, sl, _ = w.plan_inputs()
+    p = qxtn.Plan(w.network(), tree, sl, max_bitstrings=w.n_bitstrings, dry_run=True)
+    info = p.info()
+    ops = p.ops()
+    assert len(ops) == info["n_ops_const"] + info["n_ops_call"] + info["n_ops_block"]
+    phases = [o["phase"] for o in ops]
+    assert phases == sorted(phases)
+    block = [o for o in ops if o["phase"] == 2]
+    assert sum(o["flops"] for o in block) == pytest.approx(info["flops_block"])
+    gemms = [o for o in block if o["op_class"] == "gemm"]
+    assert len(gemms) == info["n_gemm_block"]
+    for o in (o for o in ops if o["op_class"] == "gemm"):
+        assert o["flops"] == pytest.approx(8.0 * o["M"] * o["N"] * o["K"] * o["batch"])
+        assert o["tile"] in qxtn.TILES
+    _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn._check(qxtn.lib().qx_plan_get_op_info(p.handle, len(ops),
+                                                                                         qxtn.OpInfo())))

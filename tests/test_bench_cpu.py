@@ -47,3 +47,25 @@ def test_traffic_reported_only_for_matching_sources():
     else:
         assert got is None
     assert bench.measured_traffic("no_such_kernel") is None
+
+
+def test_trace_calls_groups_dispatches_by_contract_call(tmp_path):
+    """The trace summaries split a kernel trace at every k_block_finish and label calls by the matrix-product
+    kernel family they launch (host logic only, on a synthetic trace)."""
+    import sqlite3
+    db = tmp_path / "t.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration integer, start integer)")
+    seq = ["void qx::k_gemm_f32<128, 64, true, true>(qx::GemmArgs)", "qx::k_simt(qx::SimtArgs)",
+           "qx::k_block_finish(qx::BlockArgs, double*)",
+           "void qx::k_gemm_bf16s<256, 128, 4, 2, 3, true, false>(qx::GemmArgs)",
+           "qx::k_block_finish(qx::BlockArgs, double*)", "qx::k_block_finish(qx::BlockArgs, double*)"]
+    for i, n in enumerate(seq):
+        con.execute("insert into kernels values (?, ?, ?)", (n, 100 + i, i))
+    con.commit()
+    rows, calls = bench.trace_calls(str(db))
+    assert len(rows) == 6
+    assert [len(c) for c in calls["c64"]] == [3]
+    assert [len(c) for c in calls["split_bf16"]] == [2]
+    assert [len(c) for c in calls[None]] == [1]
+    assert bench._tile_of(seq[3]) == "256x128" and bench._family(seq[0]) == "k_gemm_f32"

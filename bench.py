@@ -227,8 +227,8 @@ def serve_bench(args):
 
     torch.cuda.set_device(0)
     mix = SERVING
-    circs = mix.circuits()
-    srv = Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_replicas=2)
+    circs = mix.circuits(reconfigure=args.serve_reconfigure, mem_weight=args.mem_weight)
+    srv = Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_replicas=2, chunk_blocks=args.chunk_blocks)
     for name, circ, net, tree, sliced, st in circs:
         srv.register(name, net, tree, sliced, precision=args.precision, max_bitstrings=mix.max_bitstrings,
                      autotune=not args.no_autotune)
@@ -240,21 +240,30 @@ def serve_bench(args):
 
     def run(reqs, rate):
         srv.latencies.clear()
+        srv.records.clear()
         t0 = time.monotonic()
         futs = []
-        for off, which, xs in reqs:
+        for i, (off, which, xs) in enumerate(reqs):
             if rate:
                 delay = t0 + off / rate - time.monotonic()
                 if delay > 0:
                     time.sleep(delay)
             futs.append(srv.submit_amplitudes(names[which], xs))
-        for f in futs:
+            if (i + 1) % 100 == 0:
+                print(json.dumps({"progress": "submitted", "requests": i + 1,
+                                  "seconds": round(time.monotonic() - t0, 1)}), file=sys.stderr, flush=True)
+        for i, f in enumerate(futs):
             f.result()
+            if (i + 1) % 100 == 0:
+                print(json.dumps({"progress": "completed", "requests": i + 1,
+                                  "seconds": round(time.monotonic() - t0, 1)}), file=sys.stderr, flush=True)
         el = time.monotonic() - t0
         lat = np.array(srv.latencies)
+        st = srv.stats()
         return {"requests": len(reqs), "amplitudes": int(sum(len(x) for _, _, x in reqs)), "seconds": el,
                 "amplitudes_per_s": sum(len(x) for _, _, x in reqs) / el, "requests_per_s": len(reqs) / el,
-                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "queue": st["queue"], "service": st["service"], "by_circuit": st["by_circuit"]}
 
     sat = run(mix.requests(args.serve_probe), None)
     rate = 0.7 * sat["requests_per_s"]
@@ -268,10 +277,14 @@ def serve_bench(args):
            "unit": "amplitudes/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
            "dtype": DTYPES[args.precision], "data": "synthetic (seeded circuits, Poisson arrivals, bitstrings)",
            "config": {"workload": f"{mix.name}: {mix.description}", "arrival_rate_per_s": rate,
+                      "chunk_blocks": args.chunk_blocks, "planner_reconfigure": args.serve_reconfigure,
+                      "flops_per_amplitude": {c[0]: c[5]["total_flops"] for c in circs},
                       "max_bitstrings_per_call": mix.max_bitstrings, "hbm_budget_gib": args.serve_budget_gib},
            "latency_ms": {"p50": pois["p50_ms"], "p99": pois["p99_ms"]},
            "poisson": pois, "saturation": sat, "max_concurrency": st["max_concurrency"],
-           "rejected": st["rejected"], "resident_gib": st["resident_bytes"] / 2 ** 30}
+           "rejected": st["rejected"], "failed": st["failed"], "replicas_built": st["replicas_built"],
+           "replicas_evicted": st["replicas_evicted"], "resident_gib": st["resident_bytes"] / 2 ** 30,
+           "argv": " ".join(sys.argv[1:])}
     print(json.dumps(out), flush=True)
 
 
@@ -296,6 +309,133 @@ def permute_measure(rank=26, reps=10):
     gbs = 16.0 * (1 << rank) / sec / 1e9
     return {"kernel": "k_permute", "elements": 1 << rank, "avg_launch_ms": sec * 1e3, "achieved_gbs": gbs,
             "frac_of_hbm_peak": gbs * 1e9 / HBM_PEAK, "in_pos_seed": 7}
+
+
+def cgemm_probe(args):
+    """One large matrix product through qx_cgemm per forced tile (kernel-level measurement): 3 untimed calls,
+    then the average of 5 timed with events on the current stream (the split precisions' calls include the
+    operand split kernels; the kernel trace separates them)."""
+    import torch
+    from paper_2110_09894_amd import qxtn
+    torch.cuda.set_device(0)
+    M, N, K = args.cgemm_probe
+    a = torch.randn(M * K * 2, device="cuda")
+    b = torch.randn(K * N * 2, device="cuda")
+    c = torch.empty(M * N * 2, device="cuda")
+    out = {"probe": "qx_cgemm", "M": M, "N": N, "K": K, "precision": args.precision, "tiles": {}}
+    for t in args.probe_tiles.split(","):
+        for _ in range(3):
+            qxtn.cgemm(a, b, c, M, N, K, K, 1, 1, K, 0, 0, 0, 1, args.precision, tile=t)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            qxtn.cgemm(a, b, c, M, N, K, K, 1, 1, K, 0, 0, 0, 1, args.precision, tile=t)
+        e1.record()
+        torch.cuda.synchronize()
+        out["tiles"][t] = {"ms_per_call": e0.elapsed_time(e1) / 5}
+        print(json.dumps({"tile": t, "ms_per_call": out["tiles"][t]["ms_per_call"]}), flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def summarize_mfma(run_dir, out_name):
+    """MFMA-pipe busy fraction and clock of the probe's products, from a kernel trace (run_dir/trace) and one
+    counter pass per precision (run_dir/pmc_<precision>: SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE,
+    SQ_INSTS_VALU_MFMA_MOPS_*).  GRBM_GUI_ACTIVE comes summed over the 8 XCDs; per XCD it is the active
+    GPU cycles of the dispatch, so cycles / duration is the clock the kernel ran at.  The MFMA busy cycles
+    are summed over all 1024 SIMDs."""
+    import glob
+    import sqlite3
+    SIMDS, XCDS = 1024, 8
+    rows = []
+    for tdb in sorted(glob.glob(os.path.join(run_dir, "trace_*", "**", "*results.db"), recursive=True)):
+        prec = tdb.split("trace_", 1)[1].split(os.sep, 1)[0]
+        con = sqlite3.connect(tdb)
+        durs = {}
+        for name, dur in con.execute("select name, duration from kernels order by start"):
+            if _family(name):
+                durs.setdefault(name, []).append(dur)
+        cnt = {}
+        for pdb in glob.glob(os.path.join(run_dir, f"pmc_{prec}", "**", "*results.db"), recursive=True):
+            pc = sqlite3.connect(pdb)
+            for _, kname, cname, val in pc.execute(
+                    "select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+                    "group by dispatch_id, counter_name order by dispatch_id"):
+                if _family(kname):
+                    cnt.setdefault(kname, {}).setdefault(cname, []).append(val)
+        for name, ds in durs.items():
+            ds = ds[3:] or ds                      # the timed calls (3 untimed first)
+            dur = sum(ds) / len(ds) * 1e-9
+            c = cnt.get(name, {})
+            busy = (sum(c["SQ_VALU_MFMA_BUSY_CYCLES"][3:]) / len(c["SQ_VALU_MFMA_BUSY_CYCLES"][3:])
+                    if "SQ_VALU_MFMA_BUSY_CYCLES" in c else None)
+            act = (sum(c["GRBM_GUI_ACTIVE"][3:]) / len(c["GRBM_GUI_ACTIVE"][3:]) / XCDS
+                   if "GRBM_GUI_ACTIVE" in c else None)
+            rows.append((prec, _tile_of(name), name, dur, busy, act))
+    lines = [f"# MFMA-pipe occupancy and clock of single large products", "",
+             "Commands (repository root, one MI355X), per precision P:", "", "```", "cd /tmp && export TMPDIR=/tmp",
+             "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/mfma/trace_P -o run -- python3 $R/bench.py "
+             "--cgemm-probe 8192 8192 4096 --precision P --probe-tiles <tiles>",
+             "rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE SQ_INSTS_VALU_MFMA_MOPS_BF16 "
+             "SQ_INSTS_VALU_MFMA_MOPS_F16 SQ_INSTS_VALU_MFMA_MOPS_F32 -d $R/gpurun_out/mfma/pmc_P -o run -- python3 "
+             "$R/bench.py --cgemm-probe 8192 8192 4096 --precision P --probe-tiles <tiles>",
+             f"python3 $R/bench.py --summarize-mfma $R/gpurun_out/mfma {out_name}", "```", "",
+             "`busy` = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs); `clock` = active cycles per XCD /",
+             "kernel duration; `% of nominal` = executed MFMA flops / duration / the dtype's dense peak at 2.4 GHz",
+             "(= busy x clock / 2.4 GHz when the MFMAs run at their full rate).", "",
+             "| precision | tile | kernel ms | busy | clock GHz | executed TFLOP/s | % of nominal |",
+             "|---|---|---:|---:|---:|---:|---:|"]
+    for prec, tile, name, dur, busy, act in rows:
+        M = N = 8192
+        K = 4096
+        mult = 1 if prec == "c64" else 3
+        ex = 8.0 * M * N * K * mult / dur
+        b = f"{100 * busy / (act * SIMDS):.1f}%" if busy and act else "-"
+        clk = f"{act / dur / 1e9:.2f}" if act else "-"
+        lines.append(f"| {prec} | {tile} | {dur * 1e3:.3f} | {b} | {clk} | {ex / 1e12:.0f} | "
+                     f"{100 * ex / PEAKS[prec]:.1f} |")
+    path = os.path.join(PROFILES, out_name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
+def summarize_serving(out_name, logs):
+    """Serving-mix summary from bench.py --workload c5 runs (one JSON line each): throughput and latency per
+    phase, and per circuit the p50 / p99 of latency split into queue wait (arrival to first dispatch) and
+    service (first dispatch to result)."""
+    runs = [bench_line(p) for p in logs]
+    lines = ["# Serving mix (c5): continuous batching over resident plans, one MI355X", "",
+             "Commands (repository root):", "", "```"]
+    lines += [f"python3 bench.py {r.get('argv', '')}" for r in runs]
+    lines += ["```", "", runs[0]["config"]["workload"], "",
+              "Latency is arrival to result; queue = arrival to the request's first dispatch, service = first",
+              "dispatch to result (a request larger than a call's capacity is served by several calls).", "",
+              "| form | phase | requests | amplitudes | seconds | amplitudes/s | requests/s | p50 ms | p99 ms | "
+              "queue p50 / p99 ms | service p50 / p99 ms |",
+              "|---|---|---:|---:|---:|---:|---:|---:|---:|---|---|"]
+    for r in runs:
+        for ph in ("saturation", "poisson"):
+            x = r[ph]
+            lines.append(f"| {r['dtype']} | {ph} | {x['requests']} | {x['amplitudes']} | {x['seconds']:.1f} | "
+                         f"{x['amplitudes_per_s']:.0f} | {x['requests_per_s']:.2f} | {x['p50_ms']:.0f} | "
+                         f"{x['p99_ms']:.0f} | {x['queue']['p50_ms']:.0f} / {x['queue']['p99_ms']:.0f} | "
+                         f"{x['service']['p50_ms']:.0f} / {x['service']['p99_ms']:.0f} |")
+    for r in runs:
+        lines += ["", f"Poisson phase per circuit, {r['dtype']} (arrival rate {r['config']['arrival_rate_per_s']:.2f}"
+                      f"/s; max concurrent calls {r['max_concurrency']}, rejected {r['rejected']}, failed "
+                      f"{r.get('failed', 0)}, replicas built {r.get('replicas_built', '-')}, evicted "
+                      f"{r.get('replicas_evicted', '-')}, resident {r['resident_gib']:.1f} GiB):", "",
+                  "| circuit | requests | p50 ms | p99 ms | queue p50 / p99 ms | service p50 / p99 ms |",
+                  "|---|---:|---:|---:|---|---|"]
+        for name, v in r["poisson"]["by_circuit"].items():
+            lines.append(f"| {name} | {v['requests']} | {v['total']['p50_ms']:.0f} | {v['total']['p99_ms']:.0f} | "
+                         f"{v['queue']['p50_ms']:.0f} / {v['queue']['p99_ms']:.0f} | "
+                         f"{v['service']['p50_ms']:.0f} / {v['service']['p99_ms']:.0f} |")
+    path = os.path.join(PROFILES, out_name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
 
 
 def refined_note(args):
@@ -409,9 +549,13 @@ def _family(name):
 
 
 def _tile_of(name):
-    """Work-group tile from a matrix-product kernel name: the first two template arguments."""
-    args = name.split("<", 1)[1].split(">", 1)[0].split(",")
-    return f"{args[0].strip()}x{args[1].strip()}"
+    """Work-group tile from a matrix-product kernel name: the first two template arguments, with "p<stages>"
+    for the software-pipelined split-precision form (its last template argument)."""
+    args = [a.strip() for a in name.split("<", 1)[1].split(">", 1)[0].split(",")]
+    t = f"{args[0]}x{args[1]}"
+    if len(args) == 8 and args[7] == "true":
+        t += f"p{args[4]}"
+    return t
 
 
 def trace_calls(db_path):
@@ -644,10 +788,20 @@ def main():
                     help="c2: leave the M highest-numbered qubits open (2^M amplitudes per bitstring)")
     ap.add_argument("--mem-weight", type=float, default=16.0,
                     help="with --reconfigure: flop:element ratio of the roofline cost (0 = flops only)")
-    ap.add_argument("--serve-probe", type=int, default=24, help="c5: requests in the saturation probe")
-    ap.add_argument("--serve-requests", type=int, default=120, help="c5: requests in the Poisson phase")
+    ap.add_argument("--serve-probe", type=int, default=100, help="c5: requests in the saturation probe")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
+    ap.add_argument("--chunk-blocks", type=int, default=1, help="c5: slice blocks per dispatched chunk of a call")
+    ap.add_argument("--serve-reconfigure", type=int, default=2, metavar="R",
+                    help="c5: plan the pool's circuits with the best R greedy trials refined (0 = greedy trees)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--cgemm-probe", type=int, nargs=3, metavar=("M", "N", "K"),
+                    help="time one M x N x K product through qx_cgemm for each of --probe-tiles")
+    ap.add_argument("--probe-tiles", default="128x128,128x128p3", help="tiles for --cgemm-probe")
+    ap.add_argument("--summarize-serving", nargs="+", metavar="OUT_OR_LOG",
+                    help="write the serving summary profiles/OUT from c5 bench logs (OUT LOG [LOG ...])")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "OUT"),
+                    help="write the MFMA occupancy / clock table profiles/OUT from probe traces and counters")
     ap.add_argument("--permute-only", action="store_true", help="time only k_permute (2^26 elements)")
     ap.add_argument("--summarize-traffic", metavar="DIR", help="write the HBM traffic summary from counter runs")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "LOG", "OUT"),
@@ -664,8 +818,17 @@ def main():
     if args.summarize_products:
         summarize_products(*args.summarize_products)
         return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
+        return
+    if args.summarize_serving:
+        summarize_serving(args.summarize_serving[0], args.summarize_serving[1:])
+        return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cgemm_probe:
+        cgemm_probe(args)
         return
     if args.permute_only:
         import torch

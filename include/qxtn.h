@@ -100,7 +100,9 @@ typedef struct {
 } qx_plan_options;
 
 /* Work-group tile shapes (rows of A x columns of B) of the matrix-core products.
- * Options and qx_cgemm take the tile as (value + 1), 0 meaning automatic. */
+ * Options and qx_cgemm take the tile as (value + 1), 0 meaning automatic.  The P3
+ * and P4 shapes are the split-precision products' software-pipelined form (one
+ * work-group per CU, three or four LDS stages); complex64 runs them as 128x128. */
 typedef enum {
   QX_TILE_128x128 = 0,
   QX_TILE_64x64 = 1,
@@ -108,7 +110,9 @@ typedef enum {
   QX_TILE_64x128 = 3,
   QX_TILE_256x128 = 4,
   QX_TILE_128x256 = 5,
-  QX_N_TILES = 6
+  QX_TILE_128x128P3 = 6,
+  QX_TILE_128x128P4 = 7,
+  QX_N_TILES = 8
 } qx_gemm_tile;
 
 typedef struct {

@@ -371,6 +371,7 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
     // shape with the smallest time.
     std::vector<int> cand;
     for (int t = 0; t < GEMM_N_TILES; ++t) {
+      if (gemm_tile_pipelined(t) && p->pc.precision == QX_C64) continue;  // same kernel as the plain shape
       int bm, bn;
       gemm_tile_dims(t, bm, bn);
       if (bm <= std::max<int64_t>(64, g.M) && bn <= std::max<int64_t>(64, g.N)) cand.push_back(t);
@@ -446,7 +447,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
   opt.slice_batch_log2 = -1;
   if (opt_in) opt = *opt_in;
   if (opt.gemm_tile < 0 || opt.gemm_tile > GEMM_N_TILES)
-    return fail(QX_ERR_INVALID_ARG, "gemm_tile must be 0 (automatic) or 1..6 (tile + 1)");
+    return fail(QX_ERR_INVALID_ARG, "gemm_tile must be 0 (automatic) or 1..8 (tile + 1)");
   if (opt.reserved_ != 0) return fail(QX_ERR_INVALID_ARG, "reserved_ must be 0");
   if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
     return fail(QX_ERR_INVALID_ARG, "unknown precision");
@@ -904,7 +905,7 @@ static qx_status cgemm_check(const void* d_a, const void* d_b, void* d_c, int64_
                              int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t batch,
                              int32_t precision, int32_t tile_opt) {
   if (!d_a || !d_b || !d_c) return fail(QX_ERR_INVALID_ARG, "NULL argument");
-  if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..6");
+  if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..8");
   if (M < 1 || N < 1 || K < 1 || batch < 0) return fail(QX_ERR_INVALID_ARG, "M, N, K must be >= 1, batch >= 0");
   if (!(a_ms == 1 || a_ks == 1) || !(b_ks == 1 || b_ns == 1) || a_ms < 1 || a_ks < 1 || b_ks < 1 || b_ns < 1)
     return fail(QX_ERR_INVALID_ARG, "one stride of each operand must be 1 and all strides >= 1");

@@ -396,26 +396,246 @@ __device__ __forceinline__ void gemm_split16(const GemmArgs& p) {
                                                  reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
 }
 
+// A wave's fragments of one k tile: for each of its FM (FN) 32-row blocks of A (B), the four
+// planes of its lane's 8 consecutive k.
+template <class frag, int FM, int FN>
+struct Frags {
+  frag arh[FM], arl[FM], aih[FM], ail[FM], brh[FN], brl[FN], bih[FN], bil[FN];
+};
+
+template <class frag, int FM, int FN>
+__device__ __forceinline__ void read_frags(Frags<frag, FM, FN>& f, const char* bufA, const char* bufB,
+                                           const int (&fo)[4]) {
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const char* r = bufA + a * 32 * 128;
+    f.arh[a] = *(const frag*)(r + fo[0]);
+    f.arl[a] = *(const frag*)(r + fo[1]);
+    f.aih[a] = *(const frag*)(r + fo[2]);
+    f.ail[a] = *(const frag*)(r + fo[3]);
+  }
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const char* r = bufB + b * 32 * 128;
+    f.brh[b] = *(const frag*)(r + fo[0]);
+    f.brl[b] = *(const frag*)(r + fo[1]);
+    f.bih[b] = *(const frag*)(r + fo[2]);
+    f.bil[b] = *(const frag*)(r + fo[3]);
+  }
+}
+
+// The complex product of one k tile as 12 real MFMAs per accumulator pair (hi hi, hi lo, lo hi of
+// Re A Re B, Re A Im B, Im A Re B and -Im A Im B); consecutive MFMAs update different accumulators.
+template <class frag, int FM, int FN>
+__device__ __forceinline__ void mma_tile(Frags<frag, FM, FN>& f, v16f (&cr)[FM][FN], v16f (&ci)[FM][FN]) {
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.aih[a], f.brh[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.arh[a], f.brh[b], cr[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.aih[a], f.brl[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.arh[a], f.brl[b], cr[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.ail[a], f.brh[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.arl[a], f.brh[b], cr[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    f.aih[a] = neg(f.aih[a]);
+    f.ail[a] = neg(f.ail[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.arh[a], f.bih[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.aih[a], f.bih[b], cr[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.arh[a], f.bil[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.aih[a], f.bil[b], cr[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) ci[a][b] = mfma(f.arl[a], f.bih[b], ci[a][b]);
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) cr[a][b] = mfma(f.ail[a], f.bih[b], cr[a][b]);
+}
+
+// Software-pipelined form for one work-group per CU (one wavefront per SIMD, so the
+// accumulators and two fragment sets fit in its registers): NS LDS stages hold k tiles
+// t .. t + NS - 1.  Step t, after one barrier (tile t + 1 has landed; every wave's reads of
+// tile t are done, so its buffer is free), issues the copy of tile t + NS into that buffer,
+// issues the LDS reads of tile t + 1's fragments, and runs tile t's MFMAs on the fragments
+// read during step t - 1, so the reads overlap the products and a copy has NS - 1 steps to land.
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool F16>
+__device__ __forceinline__ void gemm_split16_pipe(const GemmArgs& p) {
+  using frag = typename std::conditional<F16, f16x8, bf16x8>::type;
+  constexpr int NW = WGM * WGN, NT = 64 * NW;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int ABYTES = BM * 128, BBYTES = BN * 128, BUF = ABYTES + BBYTES;
+  constexpr int STAGE = NW * 32 * 33 * 8;
+  constexpr int SMEM = NS * BUF > STAGE ? NS * BUF : STAGE;
+  static_assert(NS >= 2 && NS <= 4, "stages");
+  __shared__ __attribute__((aligned(1024))) char smem[SMEM];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const TileCoord tc = tile_coord(p, BM, BN);
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(p.a);
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(p.b);
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const OperandView va = view_a(p, nullptr), vb = view_b(p, nullptr);
+
+  typename std::conditional<A_KC, DmaTile<BM, NW>, RegTile<BM, NT>>::type sa;
+  typename std::conditional<B_KC, DmaTile<BN, NW>, RegTile<BN, NT>>::type sb;
+  if constexpr (A_KC) sa.init(va, m0, wave, lane);
+  else sa.init(va, m0, tid);
+  if constexpr (B_KC) sb.init(vb, n0, wave, lane);
+  else sb.init(vb, n0, tid);
+  constexpr int NI = decltype(sa)::NI + decltype(sb)::NI;  // direct copies per wave per k tile
+
+  const int64_t nk = (p.K + 15) / 16;  // K is a multiple of 16, or 8 (checked by the launcher)
+  int64_t kf = 0, ka = tc.aoff, kb = tc.boff;
+  // register-staged loads first, so a later wait for them leaves the direct copies in flight
+  auto fetch = [&](int bi) {
+    char* buf = smem + bi * BUF;
+    if constexpr (!A_KC) sa.load(va, A, ka);
+    if constexpr (!B_KC) sb.load(vb, B, kb);
+    if constexpr (A_KC) sa.issue(A, ka, buf, wave);
+    if constexpr (B_KC) sb.issue(B, kb, buf + ABYTES, wave);
+  };
+  auto commit = [&](int bi) {
+    char* buf = smem + bi * BUF;
+    if constexpr (!A_KC) sa.store(buf);
+    if constexpr (!B_KC) sb.store(buf + ABYTES);
+  };
+  auto advance = [&]() {
+    const int z = __builtin_ctzll(~(uint64_t)kf);
+    ka += p.a_kinc[z];
+    kb += p.b_kinc[z];
+    ++kf;
+  };
+
+  v16f cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      cr[a][b] = v16f{0};
+      ci[a][b] = v16f{0};
+    }
+
+  // prologue: tiles 0 .. NS - 1 into buffers 0 .. NS - 1; wait for tile 0
+  fetch(0);
+  commit(0);
+#pragma unroll
+  for (int j = 1; j < NS; ++j)
+    if (j < nk) {
+      advance();
+      fetch(j);
+      commit(j);
+    }
+  if (nk >= NS) wait_vm<(NS - 1) * NI>();
+  else wait_vm<0>();
+  stage_barrier();
+  if (p.K == 8) {
+    // one k tile whose upper half (k 8..15) does not exist: zero those slots
+    for (int i = tid; i < 4 * (BM + BN); i += NT) {
+      const int row = i >> 2, q = i & 3;
+      char* base = row < BM ? smem + row * 128 : smem + ABYTES + (row - BM) * 128;
+      const int r = row < BM ? row : row - BM;
+      *(u32x4*)(base + slot_of(r, 4 + q) * 16) = u32x4{0, 0, 0, 0};
+    }
+    stage_barrier();
+  }
+
+  const int frow = lane & 31;
+  int fo[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fo[q] = frow * 128 + slot_of(frow, (lane >> 5) * 4 + q) * 16;
+  const int aoff = wm * WM * 128, boff = ABYTES + wn * WN * 128;
+
+  Frags<frag, FM, FN> f0, f1;
+  read_frags(f0, smem + aoff, smem + boff, fo);
+  int cur = 0;  // buffer of tile t
+  auto pstep = [&](int64_t t, Frags<frag, FM, FN>& fc, Frags<frag, FM, FN>& fn) {
+    const bool has_next = t + 1 < nk, refill = t + NS < nk;
+    if (has_next) {
+      if (t + NS - 1 < nk) wait_vm<(NS - 2) * NI>();
+      else wait_vm<0>();
+    }
+    stage_barrier();  // this wave's reads of tile t have landed (lgkmcnt 0); tile t + 1 is visible
+    if (refill) {
+      advance();
+      fetch(cur);
+    }
+    const int nxt = cur + 1 == NS ? 0 : cur + 1;
+    if (has_next) read_frags(fn, smem + nxt * BUF + aoff, smem + nxt * BUF + boff, fo);
+    mma_tile(fc, cr, ci);
+    if (refill) commit(cur);
+    cur = nxt;
+  };
+  for (int64_t t = 0; t < nk; t += 2) {
+    pstep(t, f0, f1);
+    if (t + 1 < nk) pstep(t + 1, f1, f0);
+  }
+
+  // the last step's barrier followed every wave's last LDS read: the stage areas are free
+  const OutMap om = out_map(p, m0, n0);
+  const float f = F16 ? (p.c_split ? out_scale(p.c_scale) : 1.f) / (out_scale(p.a_scale) * out_scale(p.b_scale))
+                      : 1.f;
+  store_blocks<FM, FN, WM, WN, true, F16 ? 2 : 1>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, f,
+                                                 reinterpret_cast<QxCplx*>(smem) + wave * (32 * 33));
+}
+
 // Two wavefronts per SIMD where the LDS stages allow two work-groups per CU.
 #define QX_SPLIT16_BOUNDS \
-  __launch_bounds__(64 * WGM * WGN, (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024) ? 2 : 1)
+  __launch_bounds__(64 * WGM * WGN, (!PIPE && (WGM * WGN == 8 || NS * 128 * (BM + BN) <= 80 * 1024)) ? 2 : 1)
 
-template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
+// PIPE: the software-pipelined form, one work-group per CU.
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool PIPE>
 __global__ QX_SPLIT16_BOUNDS void k_gemm_bf16s(GemmArgs p) {
-  gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, false>(p);
+  if constexpr (PIPE) gemm_split16_pipe<BM, BN, WGM, WGN, NS, A_KC, B_KC, false>(p);
+  else gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, false>(p);
 }
-template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC>
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool PIPE>
 __global__ QX_SPLIT16_BOUNDS void k_gemm_fp16s(GemmArgs p) {
-  gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, true>(p);
+  if constexpr (PIPE) gemm_split16_pipe<BM, BN, WGM, WGN, NS, A_KC, B_KC, true>(p);
+  else gemm_split16<BM, BN, WGM, WGN, NS, A_KC, B_KC, true>(p);
 }
 
-template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool F16>
+template <int BM, int BN, int WGM, int WGN, int NS, bool A_KC, bool B_KC, bool F16, bool PIPE>
 static void launch_kernel(dim3 grid, dim3 block, hipStream_t s, const GemmArgs& a) {
-  if constexpr (F16) hipLaunchKernelGGL((k_gemm_fp16s<BM, BN, WGM, WGN, NS, A_KC, B_KC>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, A_KC, B_KC>), grid, block, 0, s, a);
+  if constexpr (F16)
+    hipLaunchKernelGGL((k_gemm_fp16s<BM, BN, WGM, WGN, NS, A_KC, B_KC, PIPE>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_gemm_bf16s<BM, BN, WGM, WGN, NS, A_KC, B_KC, PIPE>), grid, block, 0, s, a);
 }
 
-template <int BM, int BN, int WGM, int WGN, int NS, bool F16>
+template <int BM, int BN, int WGM, int WGN, int NS, bool F16, bool PIPE = false>
 static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   const int64_t nwg = tiles * (int64_t)a.n_items * (1LL << a.nh);
@@ -423,10 +643,10 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
   if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool akc = gemm_a_kc(a), bkc = gemm_b_kc(a);
   dim3 grid((unsigned)nwg), block(64 * WGM * WGN);
-  if (akc && bkc) launch_kernel<BM, BN, WGM, WGN, NS, true, true, F16>(grid, block, s, a);
-  else if (akc) launch_kernel<BM, BN, WGM, WGN, NS, true, false, F16>(grid, block, s, a);
-  else if (bkc) launch_kernel<BM, BN, WGM, WGN, NS, false, true, F16>(grid, block, s, a);
-  else launch_kernel<BM, BN, WGM, WGN, NS, false, false, F16>(grid, block, s, a);
+  if (akc && bkc) launch_kernel<BM, BN, WGM, WGN, NS, true, true, F16, PIPE>(grid, block, s, a);
+  else if (akc) launch_kernel<BM, BN, WGM, WGN, NS, true, false, F16, PIPE>(grid, block, s, a);
+  else if (bkc) launch_kernel<BM, BN, WGM, WGN, NS, false, true, F16, PIPE>(grid, block, s, a);
+  else launch_kernel<BM, BN, WGM, WGN, NS, false, false, F16, PIPE>(grid, block, s, a);
   return hipGetLastError();
 }
 
@@ -440,6 +660,8 @@ static hipError_t launch_split16(const GemmArgs& a, int tile, hipStream_t s) {
     case GEMM_TILE_64x128: return launch_bf16s<64, 128, 2, 2, 3, F16>(a, s);
     case GEMM_TILE_256x128: return launch_bf16s<256, 128, 4, 2, 3, F16>(a, s);
     case GEMM_TILE_128x256: return launch_bf16s<128, 256, 2, 4, 3, F16>(a, s);
+    case GEMM_TILE_128x128P3: return launch_bf16s<128, 128, 2, 2, 3, F16, true>(a, s);
+    case GEMM_TILE_128x128P4: return launch_bf16s<128, 128, 2, 2, 4, F16, true>(a, s);
     default: return launch_bf16s<128, 128, 2, 2, 2, F16>(a, s);
   }
 }

@@ -5,7 +5,9 @@
 
 namespace qx {
 
-// Work-group tile shapes of the matrix-core GEMMs (4 waves in a 2x2 grid).
+// Work-group tile shapes of the matrix-core GEMMs (qx_gemm_tile).  The P3 / P4 shapes are the
+// software-pipelined split-precision form with 3 / 4 LDS stages (one work-group per CU);
+// complex64 runs them as the plain 128x128 shape.
 enum GemmTile {
   GEMM_TILE_128x128 = 0,
   GEMM_TILE_64x64 = 1,
@@ -13,13 +15,17 @@ enum GemmTile {
   GEMM_TILE_64x128 = 3,
   GEMM_TILE_256x128 = 4,
   GEMM_TILE_128x256 = 5,
-  GEMM_N_TILES = 6
+  GEMM_TILE_128x128P3 = 6,
+  GEMM_TILE_128x128P4 = 7,
+  GEMM_N_TILES = 8
 };
 inline void gemm_tile_dims(int tile, int& bm, int& bn) {
-  static const int d[GEMM_N_TILES][2] = {{128, 128}, {64, 64}, {128, 64}, {64, 128}, {256, 128}, {128, 256}};
+  static const int d[GEMM_N_TILES][2] = {{128, 128}, {64, 64}, {128, 64}, {64, 128}, {256, 128},
+                                         {128, 256}, {128, 128}, {128, 128}};
   bm = d[tile][0];
   bn = d[tile][1];
 }
+inline bool gemm_tile_pipelined(int tile) { return tile >= GEMM_TILE_128x128P3; }
 // Default tile for a product of the given sizes (used without autotuning).
 int gemm_default_tile(int64_t M, int64_t N);
 

@@ -117,6 +117,6 @@ def test_cgemm_tile_argument_validated():
     a = torch.zeros(64, dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         qxtn.cgemm(a, a, a, 4, 4, 4, 4, 1, 1, 4, tile="16x16")
-    # the C-ABI itself rejects tiles outside 0..6 before launching anything
-    st = qxtn.lib().qx_cgemm(a.data_ptr(), a.data_ptr(), a.data_ptr(), 4, 4, 4, 4, 1, 1, 4, 0, 0, 0, 1, 0, 7, None)
+    # the C-ABI itself rejects tiles outside 0..8 before launching anything
+    st = qxtn.lib().qx_cgemm(a.data_ptr(), a.data_ptr(), a.data_ptr(), 4, 4, 4, 4, 1, 1, 4, 0, 0, 0, 1, 0, 9, None)
     assert st == qxtn.QX_ERR_INVALID_ARG

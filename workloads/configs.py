@@ -87,12 +87,16 @@ class ServingMix:
     planner_trials: int = 8
     description: str = ""
 
-    def circuits(self):
+    def circuits(self, reconfigure=2, mem_weight=16.0):
+        """(name, circuit, network, tree, sliced labels, stats) per pool circuit; with ``reconfigure`` = r > 0
+        the best r greedy trials are refined by local sub-tree re-ordering (as a server would plan the
+        circuits it keeps resident), else the plain seeded greedy tree."""
         out = []
         for rows, cols, depth, cseed, k in self.pool:
             circ = random_grid_circuit(rows, cols, depth, cseed)
             net = circuit_to_network(circ)
-            tree, sliced, st = plan_network(net, k, trials=self.planner_trials, seed=cseed + 7)
+            tree, sliced, st = plan_network(net, k, trials=self.planner_trials, seed=cseed + 7,
+                                            reconfigure=reconfigure, mem_weight=mem_weight)
             out.append((f"{rows}x{cols}_d{depth}", circ, net, tree, sliced, st))
         return out
 

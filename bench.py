@@ -448,6 +448,23 @@ def refined_note(args):
     return note
 
 
+def wait_with_progress(label, every=20.0):
+    """Waits for the current stream's work by polling an event recorded after it, printing a progress line
+    to stderr every ``every`` seconds (long single calls would otherwise print nothing)."""
+    import torch
+    ev = torch.cuda.Event()
+    ev.record()
+    t0 = time.monotonic()
+    last = t0
+    while not ev.query():
+        time.sleep(0.002)
+        now = time.monotonic()
+        if now - last >= every:
+            print(json.dumps({"progress": label, "seconds": round(now - t0, 1)}), file=sys.stderr, flush=True)
+            last = now
+    torch.cuda.synchronize()
+
+
 def c4_golden(args, sliced, x):
     """Oracle values of slices 0..63 of the 49-qubit workload (tests/golden/c4_slices_<tree>.json, written by
     tests/golden/make_c4_oracle.py from the FP64 oracle), or None if absent or for other inputs."""
@@ -477,17 +494,20 @@ def c4_bench(args):
     tree, sliced, st = w.plan_inputs(reconfigure=args.reconfigure, mem_weight=args.mem_weight)
     xs = w.bitstrings()
     x = torch.from_numpy(np.ascontiguousarray(xs).view(np.int64)).cuda()
+    print(json.dumps({"progress": "planning done, creating the plan"}), file=sys.stderr, flush=True)
     plan = qxtn.Plan(w.network(), tree, sliced, precision=args.precision, max_bitstrings=1,
                      autotune=not args.no_autotune)
     info = plan.info()
     bsz = 1 << info["slice_batch_log2"]
     n = max(bsz, (args.slices // bsz) * bsz)
     amp = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    print(json.dumps({"progress": "plan ready, warm-up"}), file=sys.stderr, flush=True)
     plan.contract(x, amp, (0, 2 * bsz))  # warm-up: two blocks (captures the block program)
-    torch.cuda.synchronize()
+    wait_with_progress("warm-up")
+    print(json.dumps({"progress": f"timing {n} slices"}), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     plan.contract(x, amp, (0, n))
-    torch.cuda.synchronize()
+    wait_with_progress("timed block")
     el = time.perf_counter() - t0
     flops = info["flops_block"] * (n // bsz) + info["flops_call"]
     total = 1 << len(sliced)
@@ -857,6 +877,7 @@ def main():
 
     w = configs.get(args.workload)
     tree, sliced, st = w.plan_inputs(reconfigure=args.reconfigure, mem_weight=args.mem_weight)
+    print(json.dumps({"progress": "planning done"}), file=sys.stderr, flush=True)
     xs = w.bitstrings()
     B = len(xs)
     net = w.network()
@@ -889,9 +910,11 @@ def main():
         """Plan, warm up, time exactly args.steps full contractions (graph-replayed slice blocks, no per-launch
         events), then one more contraction with every launch bracketed by HIP events (eager launches) for the
         roofline and the per-class split; then the error on slice 0 against the oracle."""
+        print(json.dumps({"progress": f"{precision}: creating the plan"}), file=sys.stderr, flush=True)
         plan = qxtn.Plan(net, tree, sliced, precision=precision, max_bitstrings=B,
                          autotune=not args.no_autotune, open_qubits=open_q)
         info = plan.info()
+        print(json.dumps({"progress": f"{precision}: plan ready, timing"}), file=sys.stderr, flush=True)
         amp = torch.zeros((B, per_x, 2), dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             plan.contract(x, amp)

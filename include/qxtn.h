@@ -102,7 +102,10 @@ typedef struct {
 /* Work-group tile shapes (rows of A x columns of B) of the matrix-core products.
  * Options and qx_cgemm take the tile as (value + 1), 0 meaning automatic.  The P3
  * and P4 shapes are the split-precision products' software-pipelined form (one
- * work-group per CU, three or four LDS stages); complex64 runs them as 128x128. */
+ * work-group per CU, three or four LDS stages); complex64 runs them as 128x128.
+ * THIN is the memory-bound kernel for products with one side of at most 32 and
+ * K of at most 32 (a thread per row of the large side, FP32 arithmetic, any
+ * storage); forced on another product it runs that product's default tile. */
 typedef enum {
   QX_TILE_128x128 = 0,
   QX_TILE_64x64 = 1,
@@ -112,7 +115,8 @@ typedef enum {
   QX_TILE_128x256 = 5,
   QX_TILE_128x128P3 = 6,
   QX_TILE_128x128P4 = 7,
-  QX_N_TILES = 8
+  QX_TILE_THIN = 8,
+  QX_N_TILES = 9
 } qx_gemm_tile;
 
 typedef struct {

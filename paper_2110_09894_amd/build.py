@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqxtn.so")
-SOURCES = ["gemm_f32.hip", "gemm_bf16.hip", "kernels.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["gemm_f32.hip", "gemm_bf16.hip", "gemm_thin.hip", "kernels.hip", "plan.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -372,6 +372,10 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
     std::vector<int> cand;
     for (int t = 0; t < GEMM_N_TILES; ++t) {
       if (gemm_tile_pipelined(t) && p->pc.precision == QX_C64) continue;  // same kernel as the plain shape
+      if (t == GEMM_TILE_THIN) {
+        if (gemm_thin_fits(g)) cand.push_back(t);
+        continue;
+      }
       int bm, bn;
       gemm_tile_dims(t, bm, bn);
       if (bm <= std::max<int64_t>(64, g.M) && bn <= std::max<int64_t>(64, g.N)) cand.push_back(t);
@@ -447,7 +451,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
   opt.slice_batch_log2 = -1;
   if (opt_in) opt = *opt_in;
   if (opt.gemm_tile < 0 || opt.gemm_tile > GEMM_N_TILES)
-    return fail(QX_ERR_INVALID_ARG, "gemm_tile must be 0 (automatic) or 1..8 (tile + 1)");
+    return fail(QX_ERR_INVALID_ARG, "gemm_tile must be 0 (automatic) or 1..9 (tile + 1)");
   if (opt.reserved_ != 0) return fail(QX_ERR_INVALID_ARG, "reserved_ must be 0");
   if (opt.precision < QX_C64 || opt.precision > QX_SPLIT_FP16)
     return fail(QX_ERR_INVALID_ARG, "unknown precision");
@@ -905,7 +909,7 @@ static qx_status cgemm_check(const void* d_a, const void* d_b, void* d_c, int64_
                              int64_t a_ms, int64_t a_ks, int64_t b_ks, int64_t b_ns, int64_t batch,
                              int32_t precision, int32_t tile_opt) {
   if (!d_a || !d_b || !d_c) return fail(QX_ERR_INVALID_ARG, "NULL argument");
-  if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..8");
+  if (tile_opt < 0 || tile_opt > GEMM_N_TILES) return fail(QX_ERR_INVALID_ARG, "tile must be 0 or 1..9");
   if (M < 1 || N < 1 || K < 1 || batch < 0) return fail(QX_ERR_INVALID_ARG, "M, N, K must be >= 1, batch >= 0");
   if (!(a_ms == 1 || a_ks == 1) || !(b_ks == 1 || b_ns == 1) || a_ms < 1 || a_ks < 1 || b_ks < 1 || b_ns < 1)
     return fail(QX_ERR_INVALID_ARG, "one stride of each operand must be 1 and all strides >= 1");
@@ -963,7 +967,7 @@ static qx_status cgemm_run(const void* d_a, const void* d_b, void* d_c, int64_t 
     g.K = kp;
     g.a_ms = kp; g.a_ks = 1; g.b_ns = kp; g.b_ks = 1;
     g.a_item = M * kp; g.b_item = N * kp;
-    g.a_split = g.b_split = 1;
+    g.a_split = g.b_split = kind;
     g.vec_a = g.vec_b = 1;
     gemm_args_setup(g);
     e = launch_gemm(g, precision, tile, s);

@@ -51,10 +51,9 @@ struct SimtArgs {
 //   A(m, k) at sum_i bit_i(m) a_rs[i] + sum_j bit_j(k) a_kst[j], etc.
 // a_kc / b_kc: k bits 0..2 are unit-stride-contiguous (8 consecutive k values
 // are 8 consecutive elements), which enables 16-byte loads along k.
-// a_split / b_split: the operand is stored split (split_format.h: BF16 planes,
-// or FP16 planes of the value times the tensor's power-of-two scale *a_scale /
-// *b_scale); c_split: C's storage, 0 complex64, 1 split BF16, 2 split FP16 of
-// C * *c_scale.
+// a_split / b_split / c_split: the operand's storage, 0 complex64, 1 split BF16
+// planes, 2 split FP16 planes of the value times the tensor's power-of-two
+// scale (*a_scale, *b_scale, *c_scale; split_format.h).
 #define QX_GEMM_BITS 32
 struct GemmArgs {
   const QxCplx *a, *b;

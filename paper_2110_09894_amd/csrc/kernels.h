@@ -7,7 +7,8 @@ namespace qx {
 
 // Work-group tile shapes of the matrix-core GEMMs (qx_gemm_tile).  The P3 / P4 shapes are the
 // software-pipelined split-precision form with 3 / 4 LDS stages (one work-group per CU);
-// complex64 runs them as the plain 128x128 shape.
+// complex64 runs them as the plain 128x128 shape.  THIN is the memory-bound kernel for
+// products with a side of at most 32 and K at most 32 (other products run their default tile).
 enum GemmTile {
   GEMM_TILE_128x128 = 0,
   GEMM_TILE_64x64 = 1,
@@ -17,15 +18,19 @@ enum GemmTile {
   GEMM_TILE_128x256 = 5,
   GEMM_TILE_128x128P3 = 6,
   GEMM_TILE_128x128P4 = 7,
-  GEMM_N_TILES = 8
+  GEMM_TILE_THIN = 8,  // memory-bound thin products (gemm_thin_fits), any precision
+  GEMM_N_TILES = 9
 };
 inline void gemm_tile_dims(int tile, int& bm, int& bn) {
   static const int d[GEMM_N_TILES][2] = {{128, 128}, {64, 64}, {128, 64}, {64, 128}, {256, 128},
-                                         {128, 256}, {128, 128}, {128, 128}};
+                                         {128, 256}, {128, 128}, {128, 128}, {32, 256}};
   bm = d[tile][0];
   bn = d[tile][1];
 }
-inline bool gemm_tile_pipelined(int tile) { return tile >= GEMM_TILE_128x128P3; }
+inline bool gemm_tile_pipelined(int tile) { return tile == GEMM_TILE_128x128P3 || tile == GEMM_TILE_128x128P4; }
+// The thin kernel's domain: one side of at most 32 rows and K at most 32.
+bool gemm_thin_fits(const GemmArgs& a);
+hipError_t launch_gemm_thin(const GemmArgs& a, hipStream_t s);
 // Default tile for a product of the given sizes (used without autotuning).
 int gemm_default_tile(int64_t M, int64_t N);
 

@@ -495,6 +495,10 @@ hipError_t launch_simt(const SimtArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gemm(const GemmArgs& a, int precision, int tile, hipStream_t s) {
+  if (tile == GEMM_TILE_THIN) {
+    if (gemm_thin_fits(a)) return launch_gemm_thin(a, s);
+    tile = gemm_default_tile(a.M, a.N);
+  }
   switch (precision) {
     case QX_SPLIT_BF16: return launch_gemm_bf16(a, tile, s);
     case QX_SPLIT_FP16: return launch_gemm_fp16(a, tile, s);

@@ -479,7 +479,7 @@ struct Compiler {
     g.b_kc = kcb;
     if (split()) {
       if (!XA.split || !XB.split) err = "internal: matrix-product operand not stored split";
-      g.a_split = g.b_split = 1;
+      g.a_split = g.b_split = split_kind();
     }
     // 16-byte loads need 8-element alignment: arena tensors are 256-byte aligned and every
     // non-k stride of a k-contiguous operand is a multiple of 8

@@ -35,7 +35,7 @@ EXPORTED = ["qx_plan_create", "qx_plan_get_info", "qx_plan_get_op_info", "qx_pla
 CGEMM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # matrix-core work-group tiles (qx_gemm_tile order); options take index + 1, 0 = automatic
-TILES = ["128x128", "64x64", "128x64", "64x128", "256x128", "128x256", "128x128p3", "128x128p4"]
+TILES = ["128x128", "64x64", "128x64", "64x128", "256x128", "128x256", "128x128p3", "128x128p4", "thin"]
 
 
 def _tile_opt(tile):

@@ -117,6 +117,23 @@ def test_cgemm_tile_argument_validated():
     a = torch.zeros(64, dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         qxtn.cgemm(a, a, a, 4, 4, 4, 4, 1, 1, 4, tile="16x16")
-    # the C-ABI itself rejects tiles outside 0..8 before launching anything
-    st = qxtn.lib().qx_cgemm(a.data_ptr(), a.data_ptr(), a.data_ptr(), 4, 4, 4, 4, 1, 1, 4, 0, 0, 0, 1, 0, 9, None)
+    # the C-ABI itself rejects tiles outside 0..9 before launching anything
+    st = qxtn.lib().qx_cgemm(a.data_ptr(), a.data_ptr(), a.data_ptr(), 4, 4, 4, 4, 1, 1, 4, 0, 0, 0, 1, 0, 10, None)
     assert st == qxtn.QX_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("M,N,K,akc,bkc", [(16, 1000, 16, True, True), (16, 1000, 16, False, False),
+                                           (512, 8, 8, True, False), (32, 333, 32, False, True),
+                                           (5, 7, 3, True, True), (257, 31, 17, False, False)])
+def test_cgemm_thin_kernel(precision, M, N, K, akc, bkc):
+    """The memory-bound thin kernel (a side of at most 32, K at most 32): each thread streams one row of the
+    large operand against the small one held in LDS, in FP32, from complex64 or split operands."""
+    got, want, bound = _gemm_case(M, N, K, akc, bkc, 3, M * 3 + N * 5 + K, precision, "thin")
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    if precision == "c64":
+        assert np.all(np.abs(got - want) <= 2 * K * 2.0 ** -23 * bound + 1e-30)
+        assert rel < 2e-6
+    else:
+        assert rel < SPLIT_REL[precision], rel
+        assert np.all(np.abs(got - want) <= 64 * SPLIT_REL[precision] * bound + 1e-30)

@@ -568,9 +568,17 @@ def _family(name):
     return None
 
 
+def _is_product(name, short):
+    """A matrix-product launch of the family ``short``, or of the thin-product kernel (any precision)."""
+    return _family(name) == short or "qx::k_gemm_thin<" in name
+
+
 def _tile_of(name):
     """Work-group tile from a matrix-product kernel name: the first two template arguments, with "p<stages>"
-    for the software-pipelined split-precision form (its last template argument)."""
+    for the software-pipelined split-precision form (its last template argument); "thin" for the
+    thin-product kernel."""
+    if "qx::k_gemm_thin<" in name:
+        return "thin"
     args = [a.strip() for a in name.split("<", 1)[1].split(">", 1)[0].split(",")]
     t = f"{args[0]}x{args[1]}"
     if len(args) == 8 and args[7] == "true":
@@ -649,7 +657,7 @@ def summarize_trace(db_path, log_path, out_name):
             continue
         short = KERNEL_NAMES[prec]
         for kind in ("timed", "evented"):
-            ds = [d for c, k in zip(cl, kinds) if k == kind for n, d in c if _family(n) == short]
+            ds = [d for c, k in zip(cl, kinds) if k == kind for n, d in c if _is_product(n, short)]
             ncall = sum(1 for k in kinds if k == kind)
             if ds:
                 out.append(f"* `{short}` ({prec}), {kind} calls ({ncall}): {len(ds)} launches, average "
@@ -715,7 +723,7 @@ def summarize_products(db_path, log_path, out_name):
             if k != "timed":
                 continue
             n_timed += 1
-            g = [(n, d) for n, d in c if _family(n) == short]
+            g = [(n, d) for n, d in c if _is_product(n, short)]
             for j, (n, d) in enumerate(g):
                 if j < len(call_ops):
                     key = ("call", j)

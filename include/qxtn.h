@@ -194,8 +194,9 @@ qx_status qx_plan_peak_bytes(const qx_plan *plan, int32_t n_bitstrings, int32_t 
  * other qubits only and d_amplitudes[b][j] receives the amplitude of x_b with
  * qubit q_i set to bit i of j (x_b's own bits at open qubits are ignored).
  * Per-slice values are formed in FP32 complex; the sum over slices and the
- * accumulation are FP64, in ascending slice order, so the result is bitwise
- * reproducible for a given plan, range and B.
+ * accumulation are FP64 in a fixed order (blocks in ascending order; inside a
+ * block, 64 ascending strided partial sums joined by a fixed butterfly), so the
+ * result is bitwise reproducible for a given plan, range and B.
  *
  *   d_bitstrings   device uint64 [B].
  *   B              1..max_bitstrings.

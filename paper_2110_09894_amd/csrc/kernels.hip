@@ -4,7 +4,7 @@
 //   k_simt      small / memory-bound pairwise contraction, any bit layout
 //   k_dot       long inner products (the root of a slice's tree); k_dot_wave for K <= 16384
 //   k_permute   LDS-tiled index permutation of dim-2 tensors
-//   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order
+//   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order, a wave per value
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)
 // The matrix-core products (Sec. IV-A: contractions mapped to matrix
 // multiplications) are in gemm_f32.hip (complex64) and gemm_bf16.hip (split BF16 / FP16).
@@ -367,12 +367,15 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 sum over the slices of one block, ascending slice order (deterministic).
-// One thread per value: bitstring v >> n_obits, open-qubit assignment j = the
-// low n_obits bits of v.
+// FP64 sum over the slices of one block in a fixed order (deterministic): one
+// wavefront per value (bitstring v >> n_obits, open-qubit assignment j = the low
+// n_obits bits of v); lane l sums slices lo + l, lo + l + 64, ... in ascending
+// order, then the 64 partial sums meet in a fixed butterfly.  A block of 2^js
+// slices thus takes about 2^js / 64 dependent steps per lane, whatever js is.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_slice_sum(SliceSumArgs p) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= p.n_items) return;
   const int item = v >> p.n_obits;
   int64_t base = (int64_t)item * p.root_item + (p.root_gather ? p.root_gather[item] : 0);
@@ -381,17 +384,24 @@ __global__ __launch_bounds__(256) void k_slice_sum(SliceSumArgs p) {
     if (i < p.n_obits && ((v >> i) & 1)) base += p.o_stride[i];
   const int lo = p.block ? (int)p.block[1] : p.s_lo, hi = p.block ? (int)p.block[2] : p.s_hi;
   double sr = 0.0, si = 0.0;
-  for (int s = lo; s < hi; ++s) {
+  for (int s = lo + lane; s < hi; s += 64) {
     int64_t off = base;
 #pragma unroll
     for (int j = 0; j < QX_MAX_SBITS; ++j)
       if (j < p.n_sbits && ((s >> j) & 1)) off += p.s_stride[j];
-    const QxCplx v = p.root[off];
-    sr += (double)v.x;
-    si += (double)v.y;
+    const QxCplx x = p.root[off];
+    sr += (double)x.x;
+    si += (double)x.y;
   }
-  p.amp[2 * (int64_t)v] += sr;
-  p.amp[2 * (int64_t)v + 1] += si;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    sr += __shfl_xor(sr, m, 64);
+    si += __shfl_xor(si, m, 64);
+  }
+  if (lane == 0) {
+    p.amp[2 * (int64_t)v] += sr;
+    p.amp[2 * (int64_t)v + 1] += si;
+  }
 }
 
 constexpr int ABSMAX_GRID = 1024;
@@ -565,7 +575,7 @@ hipError_t launch_permute(const PermArgs& a_in, hipStream_t s) {
 }
 
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.n_items + 255) / 256));
+  dim3 grid((unsigned)((a.n_items + 3) / 4));  // a wavefront per value
   hipLaunchKernelGGL(k_slice_sum, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

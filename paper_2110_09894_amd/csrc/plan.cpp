@@ -844,6 +844,14 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
         for (int j = 0; j < o.gemm.nm; ++j) fprintf(stderr, " %lld", (long long)o.gemm.a_rs[j]);
         fprintf(stderr, " b_rs");
         for (int j = 0; j < o.gemm.nn; ++j) fprintf(stderr, " %lld", (long long)o.gemm.b_rs[j]);
+        fprintf(stderr, " a_kst");
+        for (int j = 0; j < o.gemm.nk; ++j) fprintf(stderr, " %lld", (long long)o.gemm.a_kst[j]);
+        fprintf(stderr, " b_kst");
+        for (int j = 0; j < o.gemm.nk; ++j) fprintf(stderr, " %lld", (long long)o.gemm.b_kst[j]);
+        fprintf(stderr, " c_mst");
+        for (int j = 0; j < o.gemm.nm; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_mst[j]);
+        fprintf(stderr, " c_nst");
+        for (int j = 0; j < o.gemm.nn; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_nst[j]);
       }
       if (o.kind == OP_SIMT)
         fprintf(stderr, " nout %d nk %d fixa %zu fixb %zu gath %d %d", o.simt.n_out, o.simt.n_k, o.fix_a.size(),

@@ -125,10 +125,13 @@ def test_cgemm_tile_argument_validated():
 @pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("M,N,K,akc,bkc", [(16, 1000, 16, True, True), (16, 1000, 16, False, False),
                                            (512, 8, 8, True, False), (32, 333, 32, False, True),
-                                           (5, 7, 3, True, True), (257, 31, 17, False, False)])
+                                           (5, 7, 3, True, True), (257, 31, 17, False, False),
+                                           (2085, 16, 16, True, True), (20, 549, 24, True, False),
+                                           (1, 130, 1, True, True), (4096, 32, 32, True, True)])
 def test_cgemm_thin_kernel(precision, M, N, K, akc, bkc):
-    """The memory-bound thin kernel (a side of at most 32, K at most 32): each thread streams one row of the
-    large operand against the small one held in LDS, in FP32, from complex64 or split operands."""
+    """The memory-bound thin kernel (a side of at most 32, K at most 32) on the 16x16 matrix-core shapes:
+    ragged rows across blocks and waves, a short side of 1..32 (one or two 16-column blocks), K of 1..32
+    (one or two 16-k chunks), either operand the short one, k-contiguous or not."""
     got, want, bound = _gemm_case(M, N, K, akc, bkc, 3, M * 3 + N * 5 + K, precision, "thin")
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     if precision == "c64":

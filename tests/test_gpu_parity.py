@@ -71,6 +71,25 @@ def test_sliced_small_network_all_js(js):
     assert rms_err(got, want3) < TOL_C64
 
 
+@pytest.mark.parametrize("js", [6, 9])
+def test_many_slices_per_block(js):
+    """Blocks of 64 and 512 slices: each value's sum over a block is spread over a wavefront's lanes and
+    joined in a fixed butterfly; full range against the state vector, a ragged range against the sliced
+    oracle, and the same call twice bitwise."""
+    circ = random_grid_circuit(4, 4, 8, 23)
+    net = circuit_to_network(circ)
+    tree = greedy_tree(net, seed=5)
+    sl = tree_trimming(net, tree, 9, seed=5)
+    xs = random_bitstrings(16, 8, 7)
+    plan = qxtn.Plan(net, tree, sl, max_bitstrings=8, slice_batch_log2=js)
+    got = gpu_amplitudes(plan, xs)
+    assert rms_err(got, oracle.amplitudes_statevector(circ, xs)) < TOL_C64
+    assert np.array_equal(got.view(np.float64), gpu_amplitudes(plan, xs).view(np.float64))
+    rag = gpu_amplitudes(plan, xs[:2], (5, 300))
+    want = np.array([oracle.amplitude_sliced(net, tree, x, sl, (5, 300)) for x in xs[:2]])
+    assert rms_err(rag, want) < TOL_C64
+
+
 def test_ragged_slice_ranges_and_additivity():
     circ = random_grid_circuit(3, 4, 6, 22)
     net = circuit_to_network(circ)
@@ -265,6 +284,32 @@ def test_c2_slice_every_forced_tile(c2_slice777, tile, precision, tol):
     plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs), precision=precision, gemm_tile=tile)
     got = gpu_amplitudes(plan, xs, (777, 778))
     assert rms_err(got, want) < tol
+
+
+@pytest.fixture(scope="module")
+def c2r_slice777():
+    """The c2 network on the refined tree (four greedy trials re-ordered under the roofline cost), whose
+    largest products are thin (one side of 16, K = 16), and the oracle's values of slice 777 for 16 bitstrings."""
+    w = configs.get("c2")
+    net = w.network()
+    tree, sl, _ = w.plan_inputs(reconfigure=4, mem_weight=16.0)
+    xs = w.bitstrings()[:16]
+    want = np.array([oracle.contract_slice(net, tree, x, sl, 777) for x in xs])
+    return w, tree, sl, xs, want
+
+
+@pytest.mark.parametrize("tile", [None, "thin", "autotune"])
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT), ("split_fp16", TOL_SPLIT)])
+def test_c2_refined_tree_thin_products(c2r_slice777, tile, precision, tol):
+    """The refined tree's thin products in bit-scattered layouts (outputs permuted, split outputs written in
+    chunks) on the default tiles, forced onto the thin kernel, and as the autotuner picks."""
+    w, tree, sl, xs, want = c2r_slice777
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=len(xs), precision=precision,
+                     gemm_tile=None if tile == "autotune" else tile, autotune=tile == "autotune")
+    got = gpu_amplitudes(plan, xs, (777, 778))
+    err = rms_err(got, want)
+    print(f"c2 refined slice 777, {precision}, tile {tile}: max err / rms = {err:.2e}")
+    assert err < tol
 
 
 CHAIN_TREE = [(0, 1), (4, 2), (5, 3)]

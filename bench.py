@@ -408,7 +408,13 @@ def summarize_serving(out_name, logs):
     lines = ["# Serving mix (c5): continuous batching over resident plans, one MI355X", "",
              "Commands (repository root):", "", "```"]
     lines += [f"python3 bench.py {r.get('argv', '')}" for r in runs]
-    lines += ["```", "", runs[0]["config"]["workload"], "",
+    c0 = runs[0]["config"]
+    lines += ["```", "", c0["workload"], "",
+              f"Plans: trees refined by local sub-tree re-ordering of the best {c0.get('planner_reconfigure', 0)} "
+              f"greedy trials per circuit, at most {c0.get('max_bitstrings_per_call', '-')} bitstrings per call, "
+              f"calls dispatched in chunks of {c0.get('chunk_blocks', '-')} slice block(s), "
+              f"{c0.get('hbm_budget_gib', '-')} GiB HBM budget.  Complex flops per amplitude: "
+              + ", ".join(f"{k} {v:.2e}" for k, v in c0.get("flops_per_amplitude", {}).items()) + ".", "",
               "Latency is arrival to result; queue = arrival to the request's first dispatch, service = first",
               "dispatch to result (a request larger than a call's capacity is served by several calls).", "",
               "| form | phase | requests | amplitudes | seconds | amplitudes/s | requests/s | p50 ms | p99 ms | "
@@ -432,6 +438,57 @@ def summarize_serving(out_name, logs):
             lines.append(f"| {name} | {v['requests']} | {v['total']['p50_ms']:.0f} | {v['total']['p99_ms']:.0f} | "
                          f"{v['queue']['p50_ms']:.0f} / {v['queue']['p99_ms']:.0f} | "
                          f"{v['service']['p50_ms']:.0f} / {v['service']['p99_ms']:.0f} |")
+        # which circuit sets the tail, and whether waiting or service time dominates it
+        bc = r["poisson"]["by_circuit"]
+        worst = max(bc, key=lambda k: bc[k]["total"]["p99_ms"])
+        w = bc[worst]
+        part = "queue wait" if w["queue"]["p99_ms"] > w["service"]["p99_ms"] else "service time"
+        lines += ["", f"p99 attribution ({r['dtype']}): the overall p99 of {r['poisson']['p99_ms']:.0f} ms is set by "
+                      f"{worst} (p99 {w['total']['p99_ms']:.0f} ms, the largest per-circuit tail), whose tail is "
+                      f"mostly {part} (queue p99 {w['queue']['p99_ms']:.0f} ms, service p99 "
+                      f"{w['service']['p99_ms']:.0f} ms); the other circuits' p99 stay at or below "
+                      f"{max(v['total']['p99_ms'] for k, v in bc.items() if k != worst):.0f} ms."]
+    path = os.path.join(PROFILES, out_name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
+def summarize_runs(out_name, title, logs):
+    """Throughput table from bench.py runs (one JSON line each, the last line of each log): one row per
+    precision the run timed (a 30-qubit run times complex64 and both split forms), with the tree, its width,
+    executed complex TFLOP/s, the fraction of the form's peak (MFMA work for split precision) and the error
+    against the FP64 oracle (reading 12 for the 30-qubit runs, reading 18 for the 49-qubit block)."""
+    runs = [bench_line(p) for p in logs]
+    lines = [f"# {title}", "", "Commands (repository root, one MI355X):", "", "```"]
+    lines += [f"python3 bench.py {r.get('argv', '')}" for r in runs]
+    lines += ["```", "",
+              "| workload | tree | width | form | throughput | slice batch | complex TFLOP/s executed | "
+              "fraction of peak | MFMA work / peak | error vs oracle | s per amplitude (all slices) |",
+              "|---|---|---:|---|---:|---:|---:|---:|---:|---:|---:|"]
+
+    def row(r, rr, prec):
+        cfg = r["config"]
+        tree = "refined" if r.get("planner", {}).get("reconfigure") else "greedy"
+        ro = rr.get("roofline") or {}
+        e = rr.get("error_vs_oracle") or {}
+        err = e.get("max_abs_over_rms", e.get("abs_over_rss"))
+        frac = rr.get("frac_of_peak", ro.get("frac"))
+        ext = rr.get("extrapolated_seconds_per_amplitude")
+        util = ro.get("mfma_util")
+        cells = [cfg["workload"].split(":", 1)[0], tree, str(cfg.get("tree_width", "")), prec,
+                 f"{rr['value']:.1f} {r['unit']}", str(rr.get("slice_batch", cfg.get("slice_batch", ""))),
+                 f"{rr['complex_tflops']:.1f}", "" if frac is None else f"{frac:.3f}",
+                 "" if util is None else f"{util:.3f}", "(not measured)" if err is None else f"{err:.1e}",
+                 "" if ext is None else f"{ext:.0f}"]
+        lines.append("| " + " | ".join(cells) + " |")
+    for r in runs:
+        prec = r["config"].get("precision", "c64")
+        row(r, r, prec)
+        for sub in ("split_bf16", "split_fp16"):
+            if sub in r and isinstance(r[sub], dict) and "value" in r[sub]:
+                row(r, r[sub], sub)
+    lines += ["", "Workloads: " + "; ".join(sorted({r["config"]["workload"] for r in runs})) + "."]
     path = os.path.join(PROFILES, out_name)
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -826,6 +883,8 @@ def main():
     ap.add_argument("--cgemm-probe", type=int, nargs=3, metavar=("M", "N", "K"),
                     help="time one M x N x K product through qx_cgemm for each of --probe-tiles")
     ap.add_argument("--probe-tiles", default="128x128,128x128p3", help="tiles for --cgemm-probe")
+    ap.add_argument("--summarize-runs", nargs="+", metavar="ARG",
+                    help="OUT TITLE LOG...: throughput table of bench.py runs (one row per precision timed)")
     ap.add_argument("--summarize-serving", nargs="+", metavar="OUT_OR_LOG",
                     help="write the serving summary profiles/OUT from c5 bench logs (OUT LOG [LOG ...])")
     ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "OUT"),
@@ -851,6 +910,9 @@ def main():
         return
     if args.summarize_serving:
         summarize_serving(args.summarize_serving[0], args.summarize_serving[1:])
+        return
+    if args.summarize_runs:
+        summarize_runs(args.summarize_runs[0], args.summarize_runs[1], args.summarize_runs[2:])
         return
     if args.copy_calibration:
         copy_calibration()

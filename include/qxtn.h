@@ -104,7 +104,7 @@ typedef struct {
  * and P4 shapes are the split-precision products' software-pipelined form (one
  * work-group per CU, three or four LDS stages); complex64 runs them as 128x128.
  * THIN is the memory-bound kernel for products with one side of at most 32 and
- * K of at most 32 (a thread per row of the large side, FP32 arithmetic, any
+ * K of at most 32 (16x16 matrix-core shapes, independent wavefronts, any
  * storage); forced on another product it runs that product's default tile. */
 typedef enum {
   QX_TILE_128x128 = 0,

@@ -228,7 +228,8 @@ def serve_bench(args):
     torch.cuda.set_device(0)
     mix = SERVING
     circs = mix.circuits(reconfigure=args.serve_reconfigure, mem_weight=args.mem_weight)
-    srv = Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_replicas=2, chunk_blocks=args.chunk_blocks)
+    srv = Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_replicas=args.max_replicas,
+                 chunk_blocks=args.chunk_blocks)
     for name, circ, net, tree, sliced, st in circs:
         srv.register(name, net, tree, sliced, precision=args.precision, max_bitstrings=mix.max_bitstrings,
                      autotune=not args.no_autotune)
@@ -277,7 +278,8 @@ def serve_bench(args):
            "unit": "amplitudes/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
            "dtype": DTYPES[args.precision], "data": "synthetic (seeded circuits, Poisson arrivals, bitstrings)",
            "config": {"workload": f"{mix.name}: {mix.description}", "arrival_rate_per_s": rate,
-                      "chunk_blocks": args.chunk_blocks, "planner_reconfigure": args.serve_reconfigure,
+                      "chunk_blocks": args.chunk_blocks, "max_replicas": args.max_replicas,
+                      "planner_reconfigure": args.serve_reconfigure,
                       "flops_per_amplitude": {c[0]: c[5]["total_flops"] for c in circs},
                       "max_bitstrings_per_call": mix.max_bitstrings, "hbm_budget_gib": args.serve_budget_gib},
            "latency_ms": {"p50": pois["p50_ms"], "p99": pois["p99_ms"]},
@@ -411,7 +413,8 @@ def summarize_serving(out_name, logs):
     c0 = runs[0]["config"]
     lines += ["```", "", c0["workload"], "",
               f"Plans: trees refined by local sub-tree re-ordering of the best {c0.get('planner_reconfigure', 0)} "
-              f"greedy trials per circuit, at most {c0.get('max_bitstrings_per_call', '-')} bitstrings per call, "
+              f"greedy trials per circuit, at most {c0.get('max_replicas', 2)} plan replicas per circuit and "
+              f"{c0.get('max_bitstrings_per_call', '-')} bitstrings per call, "
               f"calls dispatched in chunks of {c0.get('chunk_blocks', '-')} slice block(s), "
               f"{c0.get('hbm_budget_gib', '-')} GiB HBM budget.  Complex flops per amplitude: "
               + ", ".join(f"{k} {v:.2e}" for k, v in c0.get("flops_per_amplitude", {}).items()) + ".", "",
@@ -877,6 +880,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000, help="c5: requests in the Poisson phase")
     ap.add_argument("--serve-budget-gib", type=int, default=160, help="c5: HBM budget for resident plans")
     ap.add_argument("--chunk-blocks", type=int, default=1, help="c5: slice blocks per dispatched chunk of a call")
+    ap.add_argument("--max-replicas", type=int, default=2, metavar="R",
+                    help="c5: plan replicas per circuit (each runs one call at a time on its own stream)")
     ap.add_argument("--serve-reconfigure", type=int, default=2, metavar="R",
                     help="c5: plan the pool's circuits with the best R greedy trials refined (0 = greedy trees)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")

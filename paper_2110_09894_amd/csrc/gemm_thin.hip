@@ -301,13 +301,14 @@ __global__ __launch_bounds__(256) void k_gemm_thin(ThinArgs p) {
                        (KIND == 2 ? out_scale(p.x_scale) * out_scale(p.w_scale) : 1.f);
   const int c_kind = KIND == 0 ? 0 : p.c_kind;  // complex64 operands give a complex64 product
   const bool chunked = c_kind != 0 && p.ep_chunk != 0;
-  // this lane's element of an output block (block bits 0..5), and its 8-element chunk (bits 3..)
+  // this lane's element of an output block (block bits 0..5), and the 8-element chunk whose plane
+  // lane % 4 it writes (chunk bits 3..6 = lane / 4)
   const int ep_li = (int)bit_sum<6>(lane, ei);
   const int ep_ls = (int)bit_sum<6>(lane, es);
   const int64_t ep_lo = bit_sum<6>(lane, est);
-  const int ch_i = (int)bit_sum<6>(lane, ei + 3);
-  const int ch_s = (int)bit_sum<6>(lane, es + 3);
-  const int64_t ch_o = bit_sum<6>(lane, est + 3);
+  const int qi_lane = (int)bit_sum<4>(lane >> 2, ei + 3);
+  const int qs_lane = (int)bit_sum<4>(lane >> 2, es + 3);
+  const int64_t qo_lane = bit_sum<4>(lane >> 2, est + 3);
 
   // ---- products and output, block by block
 #pragma unroll
@@ -352,29 +353,39 @@ __global__ __launch_bounds__(256) void k_gemm_thin(ThinArgs p) {
     const int64_t cb0 = cw + bit_sum<7>(blk << 4, crs);
     const int64_t rows = L - r0;  // valid rows of this block (may exceed 16)
     if (KIND != 0 && chunked && rows >= 16) {
-      // a lane converts one 8-element chunk (block bits 0..2 have output strides 1, 2, 4); S is a
-      // power of two, so a chunk is wholly inside the output (its first s below S) or wholly outside
+      // Block bits 0..2 have output strides 1, 2, 4, so the block is NE / 8 chunks of 8 elements.
+      // Four consecutive lanes write the four 16-byte planes of one chunk (plane q = hi / lo of the
+      // real / imaginary parts), so a store instruction covers 16 whole chunks, contiguous where the
+      // chunks are; a lane reads its component of the chunk's 8 values and forms its plane.  S is a
+      // power of two, so a chunk is wholly inside the output (its first s below S) or wholly outside.
       uint16_t* __restrict__ C16 = static_cast<uint16_t*>(p.c);
-      if (lane < NE / 8 && ch_s < S) {
-        const int64_t e0 = cb0 + ch_o;  // a multiple of 8
-        uint32_t pw[4][4];
+      const float* stage_f = reinterpret_cast<const float*>(stage);
+      const int q = lane & 3, comp = q >> 1;
+      const bool low = (q & 1) != 0;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          uint32_t hw[2], lw[2];
+      for (int r = 0; r < NE / 8 / 16; ++r) {
+        // chunk (lane >> 2) + 16 r: block bits 3..6 from the lane, 7 and 8 from the round
+        const int ci = qi_lane + (int)bit_sum<2>(r, ei + 7), cs = qs_lane + (int)bit_sum<2>(r, es + 7);
+        const int64_t co_ = qo_lane + bit_sum<2>(r, est + 7);
+        if (cs < S) {
+          uint32_t pw[4];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int v = 2 * d + h;
-            const int i = ch_i + (int)bit_sum<3>(v, ei), sv = ch_s + (int)bit_sum<3>(v, es);
-            split_value(c_kind, 1.f, stage[i * PITCH + sv], hw[h], lw[h]);
+          for (int d = 0; d < 4; ++d) {
+            float x[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int v = 2 * d + h;
+              const int i = ci + (int)bit_sum<3>(v, ei), sv = cs + (int)bit_sum<3>(v, es);
+              x[h] = stage_f[2 * (i * PITCH + sv) + comp];
+            }
+            // the same component of elements 2d and 2d + 1 as a pair: split_value gives their hi
+            // plane word and their lo plane word
+            uint32_t hw, lw;
+            split_value(c_kind, 1.f, QxCplx{x[0], x[1]}, hw, lw);
+            pw[d] = low ? lw : hw;
           }
-          uint32_t w[4];
-          split_words(hw[0], lw[0], hw[1], lw[1], w);
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) pw[qq][d] = w[qq];
+          *reinterpret_cast<v4u*>(C16 + split_chunk(cb0 + co_) + 8 * q) = v4u{pw[0], pw[1], pw[2], pw[3]};
         }
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq)
-          *reinterpret_cast<v4u*>(C16 + split_chunk(e0) + 8 * qq) = v4u{pw[qq][0], pw[qq][1], pw[qq][2], pw[qq][3]};
       }
     } else {
 #pragma unroll

@@ -831,8 +831,9 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
               kn[o.kind], o.in_a, pc.tensors[o.in_a].lay.size(), (int)pc.tensors[o.in_a].batched, o.in_b,
               o.out, pc.tensors[o.out].lay.size(), (int)pc.tensors[o.out].batched, o.flops, o.bytes);
       if (o.kind == OP_GEMM)
-        fprintf(stderr, " M %lld N %lld K %lld nh %d akc %d bkc %d", (long long)o.gemm.M, (long long)o.gemm.N,
-                (long long)o.gemm.K, o.gemm.nh, o.gemm.a_kc, o.gemm.b_kc);
+        fprintf(stderr, " M %lld N %lld K %lld nh %d akc %d bkc %d csplit %d epreg %d", (long long)o.gemm.M,
+                (long long)o.gemm.N, (long long)o.gemm.K, o.gemm.nh, o.gemm.a_kc, o.gemm.b_kc, o.gemm.c_split,
+                o.gemm.ep_reg);
       if (o.kind == OP_GEMM) {
         fprintf(stderr, " ep");
         for (int j = 0; j < 10; ++j) fprintf(stderr, " %s%d:%lld", o.gemm.ep_lm[j] ? "m" : "n",

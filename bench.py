@@ -84,7 +84,8 @@ def summarize_traffic(run_dir):
 
     def per_dispatch(tag, counter, kernel=None):
         """[(kernel name, value)] for every dispatch of the copy run, or, with ``kernel``, for every dispatch
-        of that kernel in the last contract call that launches it (the dispatches after one call's
+        of that kernel (and of the thin-product kernel, which serves every precision's thin products) in the
+        last contract call that launches it (the dispatches after one call's
         k_block_finish up to the next one's): the timed call of that precision, after the warm-up call
         that ran the tile autotuner."""
         dbs = glob.glob(os.path.join(run_dir, tag, "**", "*results.db"), recursive=True)
@@ -102,7 +103,7 @@ def summarize_traffic(run_dir):
                 if cur:
                     calls.append(cur)
                 cur = []
-            elif f"qx::{kernel}<" in name:
+            elif _is_product(name, kernel):
                 cur.append((name, val))
         return calls[-1] if calls else []
 

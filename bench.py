@@ -100,10 +100,12 @@ def summarize_traffic(run_dir):
         calls, cur = [], []
         for _, name, val in rows:
             if "k_block_finish" in name:
-                if cur:
-                    calls.append(cur)
+                # a call of this precision launches the family's own kernel and no other family's (thin-product
+                # launches do not tell the precision; the split FP16 plan's creation also runs complex64 products)
+                if {_family(n) for n, _ in cur} - {None} == {kernel}:
+                    calls.append([(n, v) for n, v in cur if _is_product(n, kernel)])
                 cur = []
-            elif _is_product(name, kernel):
+            else:
                 cur.append((name, val))
         return calls[-1] if calls else []
 

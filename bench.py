@@ -662,6 +662,8 @@ def trace_calls(db_path):
         cur.append((name, dur))
         if "k_block_finish" in name:
             fams = {_family(n) for n, _ in cur} - {None}
+            if len(fams) > 1:
+                fams -= {KERNEL_NAMES["c64"]}  # a split FP16 plan's creation runs a complex64 calibration block
             prec = FAMILY[fams.pop()] if len(fams) == 1 else None
             calls.setdefault(prec, []).append(cur)
             cur = []

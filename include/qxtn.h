@@ -55,9 +55,10 @@ typedef enum {
   QX_SPLIT_BF16 = 1, /* matrix products as BF16 hi+lo terms on MFMA, FP32 accumulation */
   QX_SPLIT_FP16 = 2  /* matrix products as FP16 hi+lo terms on MFMA, FP32 accumulation; each
                         operand tensor is stored times a power-of-two scale fixed at plan creation
-                        by a complex64 calibration pass (its largest magnitude then lies below 2^6,
-                        about 1000x below FP16's limit; a later value beyond that headroom gives
-                        non-finite amplitudes) */
+                        by four complex64 calibration passes over pseudo-random bitstrings and
+                        slice blocks spread over the range (its largest magnitude there then lies
+                        below 2^6, about 1000x below FP16's limit; a later value beyond that
+                        headroom gives non-finite amplitudes) */
 } qx_precision;
 
 /* The network: leaves only.  Output wires are open indices, not tensors. */

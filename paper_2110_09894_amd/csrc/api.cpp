@@ -144,8 +144,7 @@ static void resolve_pointers(qx_plan* p) {
         op.absmax.x = a;
         op.absmax.ticket = reinterpret_cast<unsigned int*>(p->d_misc);
         op.absmax.partial = p->d_misc + 64;
-        op.absmax.scale = scale_ptr(p, op.scale_slot);
-        op.absmax.target_exp = FP16_TARGET_EXP;
+        op.absmax.maxv = scale_ptr(p, op.scale_slot);
         break;
       case OP_DOT:
         op.dot.a = a; op.dot.b = b; op.dot.c = c;
@@ -298,42 +297,99 @@ static qx_status run_block(qx_plan* p, int B, hipStream_t s, int mode = MODE_RUN
   return QX_OK;
 }
 
-// Split FP16 plans: fixes every split tensor's power-of-two scale from one
-// complex64 pass (plan-time ops, per-call ops with every bitstring zero, the
-// first slice block), then rewrites the split leaves in split FP16 form and
-// recomputes the plan-time ops in it.  Later calls reuse the scales: a value
-// more than about 1000 times the calibration pass's largest of its tensor would
-// overflow FP16 and make the amplitudes it reaches non-finite.
-static qx_status calibrate_fp16(qx_plan* p, hipStream_t s, int64_t gather_bytes) {
+// Per-bitstring offsets of every output closure (one gather per OPEN -> BATCHED edge).
+static qx_status run_gathers(qx_plan* p, const uint64_t* d_bitstrings, int B, hipStream_t s) {
+  const PlanCore& pc = p->pc;
+  for (size_t g = 0; g < pc.gathers.size(); ++g) {
+    const GatherDesc& gd = pc.gathers[g];
+    GatherArgs ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.x = d_bitstrings;
+    ga.out = p->d_gather + (int64_t)g * pc.max_b;
+    ga.n_items = B;
+    ga.n_q = (int)gd.q.size();
+    for (size_t j = 0; j < gd.q.size(); ++j) {
+      ga.q[j] = gd.q[j];
+      ga.stride[j] = gd.stride[j];
+    }
+    hipError_t e = timed(p, QX_OPCLASS_GATHER, 0.0, 16.0 * B, s, [&] { return launch_gather(ga, s); });
+    if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("gather launch: ") + hipGetErrorString(e));
+  }
+  return QX_OK;
+}
+
+// Calibration passes of a split FP16 plan and the bitstrings they use: SplitMix64
+// (Steele, Lea and Flood, 2014) of the pass and item, cut to the circuit's qubits.
+constexpr int FP16_CAL_PASSES = 4;
+static uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// Split FP16 plans: fixes every split tensor's power-of-two scale from complex64
+// passes (plan-time ops once; then, per pass, the per-call ops and one slice
+// block for max_bitstrings pseudo-random bitstrings, the passes spread over the
+// slice blocks), then rewrites the split leaves in split FP16 form and recomputes
+// the plan-time ops in it.  A tensor's scale follows the largest magnitude it
+// held in any pass.  Bitstrings matter: the two-qubit gates of the random
+// circuits keep many tensor entries exactly zero, so one fixed bitstring can
+// leave whole batched tensors zero.  Later calls reuse the scales: a value more
+// than about 1000 times the largest its tensor held in calibration would overflow
+// FP16 and make the amplitudes it reaches non-finite.
+static qx_status calibrate_fp16(qx_plan* p, hipStream_t s) {
   const PlanCore& pc = p->pc;
   for (int i = 0; i < pc.n_const; ++i) {
     const qx_status r = run_op(p, pc.ops[i], 1, s, MODE_CALIBRATE);
     if (r != QX_OK) return r;
   }
-  HIP_TRY(hipMemsetAsync(p->d_gather, 0, gather_bytes, s));
-  BlockArgs ba;
-  std::memset(&ba, 0, sizeof(ba));
-  ba.state = p->d_state;
-  ba.acc = reinterpret_cast<double*>(p->d_state + 8);
-  ba.slice_end = (int64_t)1 << pc.js;
-  ba.js = pc.js;
-  ba.n_items = pc.max_b << pc.n_open;
-  HIP_TRY(launch_block_init(ba, s));
-  for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
-    const qx_status r = run_op(p, pc.ops[i], pc.max_b, s, MODE_CALIBRATE);
+  const int nq = pc.n_qubits;
+  const uint64_t qmask = nq >= 64 ? ~0ULL : ((1ULL << nq) - 1);
+  std::vector<uint64_t> bits((size_t)FP16_CAL_PASSES * pc.max_b);
+  for (size_t i = 0; i < bits.size(); ++i) bits[i] = splitmix64(0x51ce0000ULL + i) & qmask;
+  uint64_t* d_bits = nullptr;
+  HIP_TRY(hipMalloc((void**)&d_bits, bits.size() * sizeof(uint64_t)));
+  struct Free {
+    uint64_t* q;
+    ~Free() { hipFree(q); }
+  } free_bits{d_bits};
+  HIP_TRY(hipMemcpyAsync(d_bits, bits.data(), bits.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  const int64_t n_blocks = (int64_t)1 << (pc.n_sliced - pc.js);
+  for (int pass = 0; pass < FP16_CAL_PASSES; ++pass) {
+    qx_status r = run_gathers(p, d_bits + (size_t)pass * pc.max_b, pc.max_b, s);
+    if (r != QX_OK) return r;
+    const int64_t blk = pass * n_blocks / FP16_CAL_PASSES;
+    BlockArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
+    ba.state = p->d_state;
+    ba.acc = reinterpret_cast<double*>(p->d_state + 8);
+    ba.first_block = blk;
+    ba.slice_begin = blk << pc.js;
+    ba.slice_end = (blk + 1) << pc.js;
+    ba.js = pc.js;
+    ba.n_items = pc.max_b << pc.n_open;
+    HIP_TRY(launch_block_init(ba, s));
+    for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
+      r = run_op(p, pc.ops[i], pc.max_b, s, MODE_CALIBRATE);
+      if (r != QX_OK) return r;
+    }
+    r = run_block(p, pc.max_b, s, MODE_CALIBRATE);
     if (r != QX_OK) return r;
   }
-  qx_status r = run_block(p, pc.max_b, s, MODE_CALIBRATE);
-  if (r != QX_OK) return r;
+  ScaleFromMaxArgs sa{scale_ptr(p, 0), pc.n_scale_slots, FP16_TARGET_EXP};
+  HIP_TRY(launch_scale_from_max(sa, s));
   for (const Tensor& t : pc.tensors)
     if (t.is_leaf && t.split) {
       SplitInplaceArgs a{p->d_leaves + t.leaf_off, t.elems(), scale_ptr(p, t.scale_slot)};
       HIP_TRY(launch_split_inplace(a, s));
     }
   for (int i = 0; i < pc.n_const; ++i) {
-    r = run_op(p, pc.ops[i], 1, s);
+    const qx_status r = run_op(p, pc.ops[i], 1, s);
     if (r != QX_OK) return r;
   }
+  // the bitstring buffer is freed on return: wait for the passes that read it
+  HIP_TRY(hipStreamSynchronize(s));
   return QX_OK;
 }
 
@@ -582,7 +638,7 @@ qx_status qx_plan_create(const qx_network* net, const int32_t* tree, const int64
       return cleanup(QX_ERR_HIP, std::string("hipMemcpyAsync(leaves): ") + hipGetErrorString(e));
     resolve_pointers(p);
     if (p->pc.precision == QX_SPLIT_FP16) {
-      qx_status r = calibrate_fp16(p, s, gb);
+      qx_status r = calibrate_fp16(p, s);
       if (r != QX_OK) {
         std::string m = g_err;
         return cleanup(r, m);
@@ -743,21 +799,8 @@ qx_status qx_contract(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64
 static qx_status contract_enqueue(qx_plan* p, const uint64_t* d_bitstrings, int32_t B, int64_t slice_begin,
                                   int64_t slice_end, double* d_amplitudes, hipStream_t s) {
   const PlanCore& pc = p->pc;
-  for (size_t g = 0; g < pc.gathers.size(); ++g) {
-    const GatherDesc& gd = pc.gathers[g];
-    GatherArgs ga;
-    std::memset(&ga, 0, sizeof(ga));
-    ga.x = d_bitstrings;
-    ga.out = p->d_gather + (int64_t)g * pc.max_b;
-    ga.n_items = B;
-    ga.n_q = (int)gd.q.size();
-    for (size_t j = 0; j < gd.q.size(); ++j) {
-      ga.q[j] = gd.q[j];
-      ga.stride[j] = gd.stride[j];
-    }
-    hipError_t e = timed(p, QX_OPCLASS_GATHER, 0.0, 16.0 * B, s, [&] { return launch_gather(ga, s); });
-    if (e != hipSuccess) return fail(QX_ERR_HIP, std::string("gather launch: ") + hipGetErrorString(e));
-  }
+  qx_status r0 = run_gathers(p, d_bitstrings, B, s);
+  if (r0 != QX_OK) return r0;
   for (int i = pc.n_const; i < pc.n_const + pc.n_call; ++i) {
     qx_status r = run_op(p, pc.ops[i], B, s);
     if (r != QX_OK) return r;

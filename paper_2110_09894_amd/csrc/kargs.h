@@ -128,17 +128,23 @@ struct SliceSumArgs {
   int64_t o_stride[QX_MAX_OBITS];
 };
 
-// Largest magnitude of a tensor -> power-of-two scale for FP16 storage:
-//   scale[0] = 2^(target_exp - e) with max |re|, |im| < 2^e   (1 if the tensor is zero)
-// Work-groups write partial maxima; the last one to finish (ticket counter)
-// reduces them, writes the scale and resets the counter for the next launch.
+// Largest magnitude of a tensor, folded into a running maximum (one per FP16 operand
+// scale, over several calibration passes).  Work-groups write partial maxima; the last
+// one to finish (ticket counter) reduces them, updates maxv and resets the counter for
+// the next launch.
 struct AbsmaxArgs {
   const QxCplx *x;
   int64_t n;                            // complex elements
   float *partial;                       // [gridDim.x]
   unsigned int *ticket;                 // zero before the first launch; left zero after each
-  float *scale;
-  int32_t target_exp, pad_;
+  float *maxv;                          // running largest |Re|, |Im|: maxv[0] = max(maxv[0], max of x)
+};
+
+// Running maxima -> power-of-two FP16 operand scales, in place:
+//   v[i] = 2^(target_exp - e) with v[i] < 2^e (clamped to 2^-100..2^100); 1 where v[i] is zero
+struct ScaleFromMaxArgs {
+  float *v;
+  int32_t n, target_exp;
 };
 
 // Slice-block state kept on the device so one captured block program can be

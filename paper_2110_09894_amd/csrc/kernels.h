@@ -51,6 +51,7 @@ hipError_t launch_block_init(const BlockArgs& a, hipStream_t s);
 hipError_t launch_block_advance(const BlockArgs& a, hipStream_t s);
 hipError_t launch_block_finish(const BlockArgs& a, double* amp, hipStream_t s);
 hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s);  // grid <= 1024 work-groups
+hipError_t launch_scale_from_max(const ScaleFromMaxArgs& a, hipStream_t s);
 constexpr int ABSMAX_PARTIALS = 1024;
 
 }  // namespace qx

@@ -6,6 +6,7 @@
 //   k_permute   LDS-tiled index permutation of dim-2 tensors
 //   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order, a wave per value
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)
+//   k_absmax, k_scale_from_max   FP16 operand scales from calibration maxima
 // The matrix-core products (Sec. IV-A: contractions mapped to matrix
 // multiplications) are in gemm_f32.hip (complex64) and gemm_bf16.hip (split BF16 / FP16).
 #include <hip/hip_runtime.h>
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(256) void k_absmax(AbsmaxArgs p) {
   if (!last) return;
   __threadfence();
   float mm = 0.f;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) mm = fmaxf(mm, __ldg(&p.partial[i]));
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) mm = fmaxf(mm, p.partial[i]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) mm = fmaxf(mm, __shfl_xor(mm, off, 64));
   __syncthreads();
@@ -434,17 +435,24 @@ __global__ __launch_bounds__(256) void k_absmax(AbsmaxArgs p) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    float sc = 1.f;
-    if (mx > 0.f && mx < 3.0e38f) {
-      int e;
-      frexpf(mx, &e);  // mx < 2^e
-      int k = p.target_exp - e;
-      k = k > 100 ? 100 : (k < -100 ? -100 : k);
-      sc = ldexpf(1.f, k);
-    }
-    p.scale[0] = sc;
+    p.maxv[0] = fmaxf(p.maxv[0], mx);
     *p.ticket = 0u;
   }
+}
+
+__global__ __launch_bounds__(256) void k_scale_from_max(ScaleFromMaxArgs p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const float mx = p.v[i];
+  float sc = 1.f;
+  if (mx > 0.f && mx < 3.0e38f) {
+    int e;
+    frexpf(mx, &e);  // mx < 2^e
+    int k = p.target_exp - e;
+    k = k > 100 ? 100 : (k < -100 ? -100 : k);
+    sc = ldexpf(1.f, k);
+  }
+  p.v[i] = sc;
 }
 
 // Start of a contract call: block state and zeroed FP64 accumulator.
@@ -631,6 +639,12 @@ hipError_t launch_absmax(const AbsmaxArgs& a, hipStream_t s) {
   const int64_t want = (a.n + 255) / 256;
   const int grid = (int)(want < 1 ? 1 : (want > ABSMAX_GRID ? ABSMAX_GRID : want));
   hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_from_max(const ScaleFromMaxArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_from_max, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -312,6 +312,20 @@ def test_c2_refined_tree_thin_products(c2r_slice777, tile, precision, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("max_b,js", [(64, -1), (128, 0), (256, -1), (256, 0)])
+def test_fp16_calibration_refined_c2(c2r_slice777, max_b, js):
+    """Split FP16 scales of the refined c2 tree for plans sized for 64 to 256 bitstrings: with every
+    bitstring zero its fSim-type gates leave whole batched tensors exactly zero, so the calibration
+    passes use pseudo-random bitstrings; a tensor calibrated at zero would keep scale 1 and lose its
+    low halves to FP16 subnormals (an error near 1e-2)."""
+    w, tree, sl, xs, want = c2r_slice777
+    plan = qxtn.Plan(w.network(), tree, sl, max_bitstrings=max_b, precision="split_fp16", slice_batch_log2=js)
+    got = gpu_amplitudes(plan, xs, (777, 778))
+    err = rms_err(got, want)
+    print(f"c2 refined slice 777, split_fp16, max_bitstrings {max_b}, js {js}: max err / rms = {err:.2e}")
+    assert err < TOL_SPLIT
+
+
 CHAIN_TREE = [(0, 1), (4, 2), (5, 3)]
 
 

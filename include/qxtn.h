@@ -106,7 +106,10 @@ typedef struct {
  * work-group per CU, three or four LDS stages); complex64 runs them as 128x128.
  * THIN is the memory-bound kernel for products with one side of at most 32 and
  * K of at most 32 (16x16 matrix-core shapes, independent wavefronts, any
- * storage); forced on another product it runs that product's default tile. */
+ * storage), and the default for them; forced on another product it runs that
+ * product's default tile.  Split-precision products whose K is neither 8 nor a
+ * multiple of 16 (large contractions with a short side and a sum of 2 or 4
+ * terms) run THIN whatever tile is asked for. */
 typedef enum {
   QX_TILE_128x128 = 0,
   QX_TILE_64x64 = 1,

@@ -432,6 +432,7 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
         if (gemm_thin_fits(g)) cand.push_back(t);
         continue;
       }
+      if (p->pc.precision != QX_C64 && !gemm_split_k_ok(g)) continue;  // such a product runs thin
       int bm, bn;
       gemm_tile_dims(t, bm, bn);
       if (bm <= std::max<int64_t>(64, g.M) && bn <= std::max<int64_t>(64, g.N)) cand.push_back(t);

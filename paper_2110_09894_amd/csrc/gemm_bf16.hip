@@ -653,7 +653,7 @@ static hipError_t launch_bf16s(const GemmArgs& a, hipStream_t s) {
 template <bool F16>
 static hipError_t launch_split16(const GemmArgs& a, int tile, hipStream_t s) {
   // operands must be stored split, and K a multiple of the 16-wide k tile (or 8: one half tile)
-  if (!a.a_split || !a.b_split || (a.K % 16 != 0 && a.K != 8)) return hipErrorInvalidValue;
+  if (!a.a_split || !a.b_split || !gemm_split_k_ok(a)) return hipErrorInvalidValue;
   switch (tile) {
     case GEMM_TILE_64x64: return launch_bf16s<64, 64, 2, 2, 2, F16>(a, s);
     case GEMM_TILE_128x64: return launch_bf16s<128, 64, 2, 2, 3, F16>(a, s);

@@ -27,6 +27,8 @@ inline void gemm_tile_dims(int tile, int& bm, int& bn) {
   bm = d[tile][0];
   bn = d[tile][1];
 }
+// K the split BF16 / FP16 tile kernels accept (8, or a multiple of 16)
+inline bool gemm_split_k_ok(const GemmArgs& a) { return a.K % 16 == 0 || a.K == 8; }
 inline bool gemm_tile_pipelined(int tile) { return tile == GEMM_TILE_128x128P3 || tile == GEMM_TILE_128x128P4; }
 // The thin kernel's domain: one side of at most 32 rows and K at most 32.
 bool gemm_thin_fits(const GemmArgs& a);

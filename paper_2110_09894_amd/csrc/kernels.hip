@@ -513,7 +513,8 @@ hipError_t launch_simt(const SimtArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gemm(const GemmArgs& a, int precision, int tile, hipStream_t s) {
-  if (tile == GEMM_TILE_THIN) {
+  // the split tile kernels take K of 8 or a multiple of 16; shorter sums run on the thin kernel
+  if (tile == GEMM_TILE_THIN || (precision != QX_C64 && !gemm_split_k_ok(a))) {
     if (gemm_thin_fits(a)) return launch_gemm_thin(a, s);
     tile = gemm_default_tile(a.M, a.N);
   }

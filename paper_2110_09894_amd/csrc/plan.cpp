@@ -255,7 +255,13 @@ struct Compiler {
       nd.bits = set_or(set_or(nd.Fa, nd.Fb), nd.H);
       const int m = (int)nd.Fa.size(), nb = (int)nd.Fb.size(), k = (int)nd.K.size();
       const bool leaf_fixed = A.has_fixed || B.has_fixed;
+      // a large result from a long operand and a short one (at most 32 rows, at most 32 terms
+      // summed): the memory-bound thin matrix-product kernel reads the long operand once, in
+      // its own order, where one thread per output would read it scattered and once per short row
+      const bool big = (int)nd.bits.size() + (nd.batched ? logb : 0) >= 20;
+      const bool thin = std::min(m, nb) >= 1 && std::min(m, nb) <= 5 && std::max(m, nb) >= 4 && k >= 1 && k <= 5;
       if (!leaf_fixed && m >= 4 && nb >= 4 && k >= 3 && m + nb + k >= 15) nd.cls = CLS_GEMM;
+      else if (!leaf_fixed && big && thin) nd.cls = CLS_GEMM;
       else if (!leaf_fixed && k >= 8) nd.cls = CLS_DOT;  // long sums: parallel reduction, never one thread
       else nd.cls = CLS_SIMT;
       if ((int)nd.bits.size() > QX_MAX_BITS) {
@@ -518,7 +524,7 @@ struct Compiler {
       }
     }
     op.flops = 8.0 * (double)g.M * g.N * g.K * std::ldexp(1.0, g.nh) * items;
-    op.tile = gemm_default_tile(g.M, g.N);
+    op.tile = (std::min(g.M, g.N) <= 32 && g.K <= 32) ? (int)GEMM_TILE_THIN : gemm_default_tile(g.M, g.N);
   }
 
   bool emit_node(int p) {
@@ -854,9 +860,18 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
         fprintf(stderr, " c_nst");
         for (int j = 0; j < o.gemm.nn; ++j) fprintf(stderr, " %lld", (long long)o.gemm.c_nst[j]);
       }
-      if (o.kind == OP_SIMT)
+      if (o.kind == OP_SIMT) {
         fprintf(stderr, " nout %d nk %d fixa %zu fixb %zu gath %d %d", o.simt.n_out, o.simt.n_k, o.fix_a.size(),
                 o.fix_b.size(), o.gather_a, o.gather_b);
+        fprintf(stderr, " a_os");
+        for (int j = 0; j < o.simt.n_out; ++j) fprintf(stderr, " %lld", (long long)o.simt.a_os[j]);
+        fprintf(stderr, " b_os");
+        for (int j = 0; j < o.simt.n_out; ++j) fprintf(stderr, " %lld", (long long)o.simt.b_os[j]);
+        fprintf(stderr, " a_ks");
+        for (int j = 0; j < o.simt.n_k; ++j) fprintf(stderr, " %lld", (long long)o.simt.a_ks[j]);
+        fprintf(stderr, " b_ks");
+        for (int j = 0; j < o.simt.n_k; ++j) fprintf(stderr, " %lld", (long long)o.simt.b_ks[j]);
+      }
       if (o.kind == OP_PERM) {
         fprintf(stderr, " in_pos");
         for (int j = 0; j < o.perm.rank; ++j) fprintf(stderr, " %d", o.perm.in_pos[j]);

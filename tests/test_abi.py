@@ -8,7 +8,7 @@ import pytest
 
 from paper_2110_09894_amd import qxtn
 from workloads import (circuit_to_network, random_grid_circuit, greedy_tree, tree_trimming, tree_stats,
-                       Network, ghz_circuit)
+                       Network, ghz_circuit, outer_thin_network)
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qxtn.h")
 
@@ -261,3 +261,22 @@ def test_op_info_lists_the_compiled_program():
         assert o["tile"] in qxtn.TILES
     _expect(qxtn.QX_ERR_INVALID_ARG, lambda: qxtn._check(qxtn.lib().qx_plan_get_op_info(p.handle, len(ops),
                                                                                          qxtn.OpInfo())))
+
+
+@pytest.mark.parametrize("bits,short_first", [((17, 3, 2), False), ((17, 3, 2), True), ((18, 2, 1), False),
+                                              ((16, 5, 5), False)])
+def test_large_long_times_short_contraction_is_a_thin_product(bits, short_first):
+    """A contraction with at least 2^20 results, one operand of at most 32 rows and at most 32 summed
+    terms is planned as a matrix product on the thin kernel; the same shape with a small result stays a
+    small contraction (one thread per output)."""
+    net = outer_thin_network(*bits, seed=1, short_first=short_first)
+    tree = [(0, 1), (3, 2)]
+    for prec in ("c64", "split_bf16", "split_fp16"):
+        ops = qxtn.Plan(net, tree, [], max_bitstrings=2, precision=prec, dry_run=True).ops()
+        first = [o for o in ops if o["op_class"] in ("gemm", "simt")][0]
+        long_rows, short_rows = 1 << bits[0], 1 << bits[1]
+        assert first["op_class"] == "gemm" and first["tile"] == "thin", first
+        assert sorted((first["M"], first["N"])) == [short_rows, long_rows] and first["K"] == 1 << bits[2]
+    small = outer_thin_network(9, 3, 2, seed=1)
+    ops = qxtn.Plan(small, tree, [], max_bitstrings=2, dry_run=True).ops()
+    assert [o for o in ops if o["op_class"] in ("gemm", "simt")][0]["op_class"] == "simt"

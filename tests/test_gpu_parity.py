@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_2110_09894_amd import qxtn  # noqa: E402
 from workloads import (circuit_to_network, random_grid_circuit, ghz_circuit, identity_circuit,  # noqa: E402
-                       dense_chain_network,
+                       dense_chain_network, outer_thin_network,
                        mirror_circuit, greedy_tree, tree_trimming, all_bitstrings, random_bitstrings,
                        configs)
 from tests._util import rms_err, gpu_amplitudes  # noqa: E402
@@ -324,6 +324,35 @@ def test_fp16_calibration_refined_c2(c2r_slice777, max_b, js):
     err = rms_err(got, want)
     print(f"c2 refined slice 777, split_fp16, max_bitstrings {max_b}, js {js}: max err / rms = {err:.2e}")
     assert err < TOL_SPLIT
+
+
+@pytest.fixture(scope="module")
+def outer_nets():
+    """Long-times-short networks and the oracle's amplitudes of their one qubit."""
+    out = {}
+    for bits, short_first in [((17, 3, 2), False), ((17, 3, 2), True), ((18, 2, 1), False)]:
+        net = outer_thin_network(*bits, seed=3, short_first=short_first)
+        want = np.array([oracle.contract_slice(net, OUTER_TREE, x) for x in (0, 1)])
+        out[(bits, short_first)] = (net, want)
+    return out
+
+
+OUTER_TREE = [(0, 1), (3, 2)]
+
+
+@pytest.mark.parametrize("tile", [None] + qxtn.TILES)
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT), ("split_fp16", TOL_SPLIT)])
+@pytest.mark.parametrize("case", [((17, 3, 2), False), ((17, 3, 2), True), ((18, 2, 1), False)])
+def test_long_times_short_contraction(outer_nets, case, precision, tol, tile):
+    """A 2^20-result contraction of a long operand (summed labels in the middle of its layout) with a short
+    one of 4 or 8 rows over 2 or 4 terms, planned as a thin matrix product: default (thin) and every
+    forced tile (split products of K 2 or 4 always run thin) against the oracle."""
+    net, want = outer_nets[case]
+    plan = qxtn.Plan(net, OUTER_TREE, [], max_bitstrings=2, precision=precision, gemm_tile=tile)
+    got = gpu_amplitudes(plan, np.array([0, 1], np.uint64))
+    err = rms_err(got, want)
+    print(f"long x short {case}, {precision}, tile {tile}: max err / rms = {err:.2e}")
+    assert err < tol
 
 
 CHAIN_TREE = [(0, 1), (4, 2), (5, 3)]

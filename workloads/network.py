@@ -102,3 +102,35 @@ def dense_chain_network(group_bits: int = 5, slow_first=(True, True, True, True)
         tensors.append(data)
         indices.append(tuple(ix))
     return Network(tensors, indices, groups[0] + groups[4], 2 * g, name=f"chain{g}")
+
+
+def outer_thin_network(long_bits: int, short_bits: int, sum_bits: int, seed: int = 0,
+                       short_first: bool = False) -> Network:
+    """Three dense random leaves: a long operand L(l, k), a short one S(s, k) and a closing leaf
+    C(l, s, q) whose one open wire q is qubit 0.  Contracted along ((L, S), C), the first product has
+    2^(long_bits + short_bits) entries summed over 2^sum_bits terms.  L lists its k labels between
+    its l labels, so neither its fastest nor its slowest labels are all summed.  ``short_first``
+    puts S first in the leaf list.  Entries are complex normal, scaled so the amplitudes are of order 1.
+    """
+    rng = np.random.default_rng(seed)
+    lo = list(range(long_bits))
+    sh = list(range(long_bits, long_bits + short_bits))
+    ks = list(range(long_bits + short_bits, long_bits + short_bits + sum_bits))
+    q = long_bits + short_bits + sum_bits
+    half = long_bits // 2
+    ix_l = tuple(lo[:half] + ks + lo[half:])
+    ix_s = tuple(ks + sh)
+    ix_c = tuple(sh + lo + [q])
+
+    def rnd(n, scale):
+        shape = (2,) * n
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * scale
+
+    t_l = rnd(len(ix_l), 2.0 ** (-0.25 * sum_bits) / np.sqrt(2.0))
+    t_s = rnd(len(ix_s), 2.0 ** (-0.25 * sum_bits) / np.sqrt(2.0))
+    t_c = rnd(len(ix_c), 2.0 ** (-0.5 * (long_bits + short_bits)) / np.sqrt(2.0))
+    tensors, indices = [t_l, t_s, t_c], [ix_l, ix_s, ix_c]
+    if short_first:
+        tensors[0], tensors[1] = tensors[1], tensors[0]
+        indices[0], indices[1] = indices[1], indices[0]
+    return Network(tensors, indices, [q], 1, name=f"outer{long_bits}x{short_bits}k{sum_bits}")

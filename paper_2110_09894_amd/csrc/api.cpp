@@ -64,7 +64,7 @@ struct qx_plan {
   char* d_arena = nullptr;
   int64_t* d_gather = nullptr;
   float* d_misc = nullptr;            // FP16 operand scales, absmax partials, absmax ticket
-  int64_t* d_state = nullptr;         // slice-block state (8 int64) then the FP64 accumulator [max_b][2]
+  int64_t* d_state = nullptr;         // slice-block state (8 int64), FP64 accumulator [max_b][2], dot partials
   int64_t device_bytes = 0;
   bool eager = false;
   hipStream_t cap_stream = nullptr;   // stream used to capture block programs
@@ -79,7 +79,14 @@ struct qx_plan {
   qx_plan_options opt{};
 };
 
-static int64_t state_bytes(const PlanCore& pc) { return 64 + ((int64_t)pc.max_b << pc.n_open) * 16; }
+// d_state: slice-block state (64 bytes), the FP64 accumulator, then (plans with a long inner product)
+// the partial sums of inner products split over work-groups
+static int64_t acc_bytes(const PlanCore& pc) { return ((int64_t)pc.max_b << pc.n_open) * 16; }
+static int64_t state_bytes(const PlanCore& pc) {
+  bool dot = false;
+  for (const Op& o : pc.ops) dot = dot || o.kind == OP_DOT;
+  return 64 + acc_bytes(pc) + (dot ? (int64_t)QX_DOT_PART_ELEMS * 8 : 0);
+}
 
 static int64_t misc_bytes(const PlanCore& pc) {
   return ((int64_t)pc.n_scale_slots + ABSMAX_PARTIALS + 64) * 4;
@@ -151,6 +158,7 @@ static void resolve_pointers(qx_plan* p) {
         op.dot.a_gather = gather_ptr(p, op.gather_a);
         op.dot.b_gather = gather_ptr(p, op.gather_b);
         op.dot.c_scale = cs;
+        op.dot.part = reinterpret_cast<QxCplx*>(reinterpret_cast<char*>(p->d_state) + 64 + acc_bytes(p->pc));
         break;
       case OP_PERM:
         op.perm.in = a; op.perm.out = c;

@@ -83,11 +83,16 @@ struct GemmArgs {
   int64_t a_kinc[QX_GEMM_BITS], b_kinc[QX_GEMM_BITS];
 };
 
-// Long inner products (root of a slice's tree): one work-group per output element.
+// Long inner products (root of a slice's tree):
 //   C[item][o] = sum_{k<K} A[..o..][k] * B[..o..][k]   (k contiguous in both)
+// Output bits fastest first: those of B only, those of A only, those of both.
+// Scratch for sums split over work-groups: at most QX_DOT_PART_ELEMS complex values.
+#define QX_DOT_PART_ELEMS (2048 * 64)
+
 struct DotArgs {
   const QxCplx *a, *b;
   QxCplx *c;
+  QxCplx *part;                         // QX_DOT_PART_ELEMS of scratch for split sums, or null
   int64_t K;
   int64_t a_item, b_item, c_item;
   const int64_t *a_gather, *b_gather;

@@ -42,6 +42,7 @@ hipError_t launch_gemm_c64(const GemmArgs& a, int tile, hipStream_t s);
 hipError_t launch_gemm_bf16(const GemmArgs& a, int tile, hipStream_t s);  // operands stored split BF16
 hipError_t launch_gemm_fp16(const GemmArgs& a, int tile, hipStream_t s);  // operands stored split FP16
 hipError_t launch_dot(const DotArgs& a, hipStream_t s);
+bool dot_outer_shape(const DotArgs& a, int& nfa, int& nfb);  // k_dot_outer applies (needs a.part)
 void permute_setup(PermArgs& a);  // fills the tile / outer-bit fields from rank and in_pos
 void gemm_args_setup(GemmArgs& g);  // fills the epilogue bit order and the k-tile steps
 hipError_t launch_permute(const PermArgs& a, hipStream_t s);

@@ -217,6 +217,151 @@ __global__ __launch_bounds__(256) void k_dot_wave(DotArgs p) {
   }
 }
 
+// Long inner products whose outputs form an NA x NB outer product per value of
+// the shared bits h (A only bits Fa, B only bits Fb, 2 <= NA, NB <= 8): a
+// work-group owns one (item, h) and a range of k, reads each of the NA rows of
+// A and NB rows of B once (16-byte loads along k) and keeps all NA * NB partial
+// sums per lane, instead of one work-group per output re-reading a row NB (NA)
+// times.  Lanes are reduced by a reduce-scatter butterfly (after step s a lane
+// keeps half of its remaining sums: the one it holds at the end is lane >> (6 -
+// log2(NA NB))), then the 4 waves through LDS, in a fixed order.  With the k
+// range split over ks work-groups the partial results go to p.part and
+// k_dot_outer_finish adds them in split order.
+template <int NA, int NB>
+__global__ __launch_bounds__(256) void k_dot_outer(DotArgs p, int nfa, int nfb, int kslog) {
+  constexpr int NACC = NA * NB;
+  constexpr int LOG = NACC >= 64 ? 6 : (NACC >= 32 ? 5 : (NACC >= 16 ? 4 : (NACC >= 8 ? 3 : 2)));
+  __shared__ float red[2][4][NACC];
+  const int nh = p.n_out - nfa - nfb;
+  const int64_t gid = blockIdx.x;
+  const int64_t split = gid & ((1LL << kslog) - 1), wg = gid >> kslog;
+  const int64_t h = wg & ((1LL << nh) - 1);
+  const int item = (int)(wg >> nh);
+  int64_t ao = (int64_t)item * p.a_item + (p.a_gather ? p.a_gather[item] : 0);
+  int64_t bo = (int64_t)item * p.b_item + (p.b_gather ? p.b_gather[item] : 0);
+#pragma unroll
+  for (int i = 0; i < QX_MAX_BITS; ++i)
+    if (i < nh && ((h >> i) & 1)) { ao += p.a_os[nfa + nfb + i]; bo += p.b_os[nfa + nfb + i]; }
+  int64_t ar[NA], br[NB];
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    ar[r] = ao;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < nfa && ((r >> j) & 1)) ar[r] += p.a_os[nfb + j];
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    br[r] = bo;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < nfb && ((r >> j) & 1)) br[r] += p.b_os[j];
+  }
+  float vr[NACC], vi[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) vr[i] = vi[i] = 0.f;
+  const int64_t kc = p.K >> kslog, k0 = split * kc, k1 = k0 + kc;
+  const int tid = threadIdx.x;
+  // rows start at multiples of K (>= 1024) past 16-byte aligned bases
+  const bool vec = ((((uintptr_t)(p.a + ao)) | ((uintptr_t)(p.b + bo))) & 15) == 0 && (p.K & 3) == 0;
+  if (vec) {
+    for (int64_t k = k0 + 2 * tid; k < k1; k += 512) {
+      v4f xa[NA], xb[NB];
+#pragma unroll
+      for (int r = 0; r < NA; ++r) xa[r] = *(const v4f*)(p.a + ar[r] + k);
+#pragma unroll
+      for (int r = 0; r < NB; ++r) xb[r] = *(const v4f*)(p.b + br[r] + k);
+#pragma unroll
+      for (int ra = 0; ra < NA; ++ra)
+#pragma unroll
+        for (int rb = 0; rb < NB; ++rb) {
+          const int i = ra * NB + rb;
+          float re = vr[i], im = vi[i];
+          re = fmaf(xa[ra][0], xb[rb][0], re);
+          re = fmaf(-xa[ra][1], xb[rb][1], re);
+          im = fmaf(xa[ra][0], xb[rb][1], im);
+          im = fmaf(xa[ra][1], xb[rb][0], im);
+          re = fmaf(xa[ra][2], xb[rb][2], re);
+          re = fmaf(-xa[ra][3], xb[rb][3], re);
+          im = fmaf(xa[ra][2], xb[rb][3], im);
+          im = fmaf(xa[ra][3], xb[rb][2], im);
+          vr[i] = re;
+          vi[i] = im;
+        }
+    }
+  } else {
+    for (int64_t k = k0 + tid; k < k1; k += 256) {
+      QxCplx xa[NA], xb[NB];
+#pragma unroll
+      for (int r = 0; r < NA; ++r) xa[r] = p.a[ar[r] + k];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) xb[r] = p.b[br[r] + k];
+#pragma unroll
+      for (int ra = 0; ra < NA; ++ra)
+#pragma unroll
+        for (int rb = 0; rb < NB; ++rb) {
+          const QxCplx c = cmul_acc(QxCplx{vr[ra * NB + rb], vi[ra * NB + rb]}, xa[ra], xb[rb]);
+          vr[ra * NB + rb] = c.x;
+          vi[ra * NB + rb] = c.y;
+        }
+    }
+  }
+  // reduce-scatter over the wave: at offset d a lane keeps the upper half of its sums if bit d is set
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int st = 0; st < LOG; ++st) {
+    const int d = 32 >> st, half = NACC >> (st + 1);
+    const bool up = (lane & d) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float sr = up ? vr[i] : vr[i + half], si = up ? vi[i] : vi[i + half];
+      const float kr = up ? vr[i + half] : vr[i], ki = up ? vi[i + half] : vi[i];
+      vr[i] = kr + __shfl_xor(sr, d, 64);
+      vi[i] = ki + __shfl_xor(si, d, 64);
+    }
+  }
+#pragma unroll
+  for (int d = 32 >> LOG; d >= 1; d >>= 1) {
+    vr[0] += __shfl_xor(vr[0], d, 64);
+    vi[0] += __shfl_xor(vi[0], d, 64);
+  }
+  if ((lane & ((64 >> LOG) - 1)) == 0) {
+    red[0][wave][lane >> (6 - LOG)] = vr[0];
+    red[1][wave][lane >> (6 - LOG)] = vi[0];
+  }
+  __syncthreads();
+  if (tid < NACC) {
+    const QxCplx r = {(red[0][0][tid] + red[0][1][tid]) + (red[0][2][tid] + red[0][3][tid]),
+                      (red[1][0][tid] + red[1][1][tid]) + (red[1][2][tid] + red[1][3][tid])};
+    if (kslog > 0) {
+      p.part[gid * NACC + tid] = r;
+    } else {
+      const int64_t e = (int64_t)item * p.c_item + h * NACC + tid;
+      if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), e, r, p.c_split, out_scale(p.c_scale));
+      else p.c[e] = r;
+    }
+  }
+}
+
+// Sums of k_dot_outer's split partial results, in split order: one thread per output.
+__global__ __launch_bounds__(256) void k_dot_outer_finish(DotArgs p, int nacc, int nh, int kslog) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = ((int64_t)p.n_items << nh) * nacc;
+  if (g >= n) return;
+  const int64_t wg = g / nacc, t = g - wg * nacc;
+  QxCplx r = {0.f, 0.f};
+  for (int64_t sp = 0; sp < (1LL << kslog); ++sp) {
+    const QxCplx v = p.part[((wg << kslog) + sp) * nacc + t];
+    r.x += v.x;
+    r.y += v.y;
+  }
+  const int64_t h = wg & ((1LL << nh) - 1);
+  const int item = (int)(wg >> nh);
+  const int64_t e = (int64_t)item * p.c_item + h * nacc + t;
+  if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), e, r, p.c_split, out_scale(p.c_scale));
+  else p.c[e] = r;
+}
+
 // Complex64 matrices -> split BF16 form [item][row][kp], k >= K zero-filled.
 __global__ __launch_bounds__(256) void k_split_planes(SplitPlanesArgs p) {
   const int64_t per = p.rows * p.kp;
@@ -532,7 +677,52 @@ int gemm_default_tile(int64_t M, int64_t N) {
   return GEMM_TILE_64x64;
 }
 
+// Outer-product form of a dot (k_dot_outer): the lowest nfb output bits are B's only, the next nfa A's
+// only, the rest shared; 1 <= nfa, nfb <= 3 and K >= 1024.
+bool dot_outer_shape(const DotArgs& a, int& nfa, int& nfb) {
+  nfa = nfb = 0;
+  int i = 0;
+  while (i < a.n_out && a.a_os[i] == 0 && a.b_os[i] != 0) ++i, ++nfb;
+  while (i < a.n_out && a.b_os[i] == 0 && a.a_os[i] != 0) ++i, ++nfa;
+  for (; i < a.n_out; ++i)
+    if (a.a_os[i] == 0 || a.b_os[i] == 0) return false;
+  return a.part != nullptr && nfa >= 1 && nfa <= 3 && nfb >= 1 && nfb <= 3 && a.K >= 1024;
+}
+
+template <int NA, int NB>
+static void launch_outer(const DotArgs& a, int nfa, int nfb, int kslog, int64_t nwg, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_outer<NA, NB>), dim3((unsigned)nwg), dim3(256), 0, s, a, nfa, nfb, kslog);
+}
+
 hipError_t launch_dot(const DotArgs& a, hipStream_t s) {
+  int nfa, nfb;
+  if (dot_outer_shape(a, nfa, nfb)) {
+    const int nh = a.n_out - nfa - nfb;
+    const int64_t wgs = (int64_t)a.n_items << nh;
+    const int nacc = 1 << (nfa + nfb);
+    // split the sum while the grid is short of 1024 work-groups (chunks of at least 4096 terms)
+    int kslog = 0;
+    while ((wgs << kslog) < 1024 && (a.K & (a.K - 1)) == 0 && (a.K >> (kslog + 1)) >= 4096) ++kslog;
+    if (kslog > 0 && (wgs << kslog) * nacc > QX_DOT_PART_ELEMS) kslog = 0;
+    const int64_t nwg = wgs << kslog;
+    if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (nfa * 4 + nfb) {
+      case 1 * 4 + 1: launch_outer<2, 2>(a, nfa, nfb, kslog, nwg, s); break;
+      case 1 * 4 + 2: launch_outer<2, 4>(a, nfa, nfb, kslog, nwg, s); break;
+      case 1 * 4 + 3: launch_outer<2, 8>(a, nfa, nfb, kslog, nwg, s); break;
+      case 2 * 4 + 1: launch_outer<4, 2>(a, nfa, nfb, kslog, nwg, s); break;
+      case 2 * 4 + 2: launch_outer<4, 4>(a, nfa, nfb, kslog, nwg, s); break;
+      case 2 * 4 + 3: launch_outer<4, 8>(a, nfa, nfb, kslog, nwg, s); break;
+      case 3 * 4 + 1: launch_outer<8, 2>(a, nfa, nfb, kslog, nwg, s); break;
+      case 3 * 4 + 2: launch_outer<8, 4>(a, nfa, nfb, kslog, nwg, s); break;
+      default: launch_outer<8, 8>(a, nfa, nfb, kslog, nwg, s); break;
+    }
+    if (kslog > 0) {
+      const int64_t n = wgs * nacc;
+      hipLaunchKernelGGL(k_dot_outer_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, nacc, nh, kslog);
+    }
+    return hipGetLastError();
+  }
   if (a.K <= 16384) {
     const int64_t n = 1LL << a.n_out;
     if (a.K >= 1024) {

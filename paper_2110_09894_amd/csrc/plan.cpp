@@ -872,6 +872,12 @@ qx_status compile_plan(const qx_network* net, const int32_t* tree, const int64_t
         fprintf(stderr, " b_ks");
         for (int j = 0; j < o.simt.n_k; ++j) fprintf(stderr, " %lld", (long long)o.simt.b_ks[j]);
       }
+      if (o.kind == OP_DOT) {
+        fprintf(stderr, " K %lld nout %d a_os", (long long)o.dot.K, o.dot.n_out);
+        for (int j = 0; j < o.dot.n_out; ++j) fprintf(stderr, " %lld", (long long)o.dot.a_os[j]);
+        fprintf(stderr, " b_os");
+        for (int j = 0; j < o.dot.n_out; ++j) fprintf(stderr, " %lld", (long long)o.dot.b_os[j]);
+      }
       if (o.kind == OP_PERM) {
         fprintf(stderr, " in_pos");
         for (int j = 0; j < o.perm.rank; ++j) fprintf(stderr, " %d", o.perm.in_pos[j]);

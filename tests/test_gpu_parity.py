@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_2110_09894_amd import qxtn  # noqa: E402
 from workloads import (circuit_to_network, random_grid_circuit, ghz_circuit, identity_circuit,  # noqa: E402
-                       dense_chain_network, outer_thin_network,
+                       dense_chain_network, outer_thin_network, dot_pair_network,
                        mirror_circuit, greedy_tree, tree_trimming, all_bitstrings, random_bitstrings,
                        configs)
 from tests._util import rms_err, gpu_amplitudes  # noqa: E402
@@ -352,6 +352,27 @@ def test_long_times_short_contraction(outer_nets, case, precision, tol, tile):
     got = gpu_amplitudes(plan, np.array([0, 1], np.uint64))
     err = rms_err(got, want)
     print(f"long x short {case}, {precision}, tile {tile}: max err / rms = {err:.2e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", TOL_C64), ("split_bf16", TOL_SPLIT)])
+@pytest.mark.parametrize("bits,sliced", [((3, 3, 14), ()), ((3, 3, 14), (6, 7)), ((1, 2, 12), ()),
+                                         ((2, 3, 10), ()), ((3, 1, 13), ()), ((2, 2, 16), (4, 5, 6))])
+def test_long_inner_product_as_outer_product(bits, sliced, precision, tol):
+    """A root inner product whose outputs are an outer product of A-only and B-only output wires (2 to 8 of
+    each) per value of the varying sliced bits, on the kernel that reads each operand row once; with one
+    slice block and 2^13 or more terms the sum is split over work-groups and the partial sums added in a
+    second pass.  Every bitstring against the oracle's unsliced contraction."""
+    net = dot_pair_network(*bits, seed=2)
+    tree = [(0, 1)]
+    n = bits[0] + bits[1]
+    xs = all_bitstrings(n)
+    want = np.array([oracle.contract_slice(net, tree, x) for x in xs])
+    plan = qxtn.Plan(net, tree, list(sliced), max_bitstrings=len(xs), precision=precision,
+                     slice_batch_log2=len(sliced))
+    got = gpu_amplitudes(plan, xs)
+    err = rms_err(got, want)
+    print(f"outer dot {bits} sliced {sliced}, {precision}: max err / rms = {err:.2e}")
     assert err < tol
 
 

@@ -134,3 +134,22 @@ def outer_thin_network(long_bits: int, short_bits: int, sum_bits: int, seed: int
         tensors[0], tensors[1] = tensors[1], tensors[0]
         indices[0], indices[1] = indices[1], indices[0]
     return Network(tensors, indices, [q], 1, name=f"outer{long_bits}x{short_bits}k{sum_bits}")
+
+
+def dot_pair_network(a_bits: int, b_bits: int, sum_bits: int, seed: int = 0) -> Network:
+    """Two dense random leaves A(qa, k) and B(qb, k) whose one contraction is a long inner product:
+    qa are the output wires of qubits 0..a_bits-1, qb those of the next b_bits qubits, k the
+    sum_bits summed labels (listed last, so fastest-varying).  Entries are complex normal, scaled
+    so the amplitudes are of order 1."""
+    rng = np.random.default_rng(seed)
+    qa = list(range(a_bits))
+    qb = list(range(a_bits, a_bits + b_bits))
+    ks = list(range(a_bits + b_bits, a_bits + b_bits + sum_bits))
+    scale = 2.0 ** (-0.25 * sum_bits) / np.sqrt(2.0)
+    tensors, indices = [], []
+    for q in (qa, qb):
+        ix = tuple(q + ks)
+        shape = (2,) * len(ix)
+        tensors.append((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * scale)
+        indices.append(ix)
+    return Network(tensors, indices, qa + qb, a_bits + b_bits, name=f"dot{a_bits}x{b_bits}k{sum_bits}")

@@ -696,16 +696,17 @@ static void launch_outer(const DotArgs& a, int nfa, int nfb, int kslog, int64_t 
 
 hipError_t launch_dot(const DotArgs& a, hipStream_t s) {
   int nfa, nfb;
-  if (dot_outer_shape(a, nfa, nfb)) {
+  // (a grid beyond 2^31 work-groups keeps the per-output kernels)
+  if (dot_outer_shape(a, nfa, nfb) && a.n_out - nfa - nfb < 31 &&
+      ((int64_t)a.n_items << (a.n_out - nfa - nfb)) <= 0x7fffffffLL) {
     const int nh = a.n_out - nfa - nfb;
     const int64_t wgs = (int64_t)a.n_items << nh;
     const int nacc = 1 << (nfa + nfb);
     // split the sum while the grid is short of 1024 work-groups (chunks of at least 4096 terms)
     int kslog = 0;
     while ((wgs << kslog) < 1024 && (a.K & (a.K - 1)) == 0 && (a.K >> (kslog + 1)) >= 4096) ++kslog;
-    if (kslog > 0 && (wgs << kslog) * nacc > QX_DOT_PART_ELEMS) kslog = 0;
+    if (kslog > 0 && ((wgs << kslog) > 0x7fffffffLL || (wgs << kslog) * nacc > QX_DOT_PART_ELEMS)) kslog = 0;
     const int64_t nwg = wgs << kslog;
-    if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
     switch (nfa * 4 + nfb) {
       case 1 * 4 + 1: launch_outer<2, 2>(a, nfa, nfb, kslog, nwg, s); break;
       case 1 * 4 + 2: launch_outer<2, 4>(a, nfa, nfb, kslog, nwg, s); break;

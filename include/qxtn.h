@@ -124,7 +124,8 @@ typedef enum {
 } qx_gemm_tile;
 
 typedef struct {
-  int64_t device_bytes;        /* device memory the plan holds (leaves, constants, arena) */
+  int64_t device_bytes;        /* device memory the plan holds (leaves, constants, arena, per-call
+                                  state; 1 MiB of inner-product partial sums in plans that have one) */
   int64_t arena_bytes;         /* part of device_bytes used as per-call working memory */
   int32_t n_leaves;
   int32_t n_sliced;

@@ -2,7 +2,9 @@
 // contraction (Sec. III-B: slicing, permuting, contracting, recombination).
 //
 //   k_simt      small / memory-bound pairwise contraction, any bit layout
-//   k_dot       long inner products (the root of a slice's tree); k_dot_wave for K <= 16384
+//   k_dot_outer long inner products whose outputs form an outer product per shared
+//               index value (the root of a slice block's tree): every operand row read once
+//   k_dot       other long inner products; k_dot_wave for K <= 16384
 //   k_permute   LDS-tiled index permutation of dim-2 tensors
 //   k_slice_sum FP64 sum of per-slice values (Eq. 2), fixed order, a wave per value
 //   k_gather    per-bitstring offsets for the output closure (Sec. II)

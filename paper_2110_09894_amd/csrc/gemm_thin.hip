@@ -114,7 +114,8 @@ __device__ __forceinline__ int64_t bit_sum(int v, const T* st) {
   return o;
 }
 
-// KIND: operand storage; KP: K rounded up to 16 or 32; SP: S rounded up to 16 or 32; XKC: X is
+// KIND: operand storage; KP: K rounded up to 16 or 32 (complex64 also 4 or 8); SP: S rounded up to
+// 16 or 32; XKC: X is
 // k-contiguous (16-byte fragment loads).  Every load is issued unconditionally (lanes outside an
 // operand read a valid element of it), so no load waits behind a branch.
 template <int KIND, int KP, int SP, bool XKC>
@@ -529,12 +530,32 @@ static void thin_args(const GemmArgs& g, ThinArgs& t) {
 
 template <int KIND, int KP, int SP>
 static void launch_thin(const ThinArgs& t, unsigned nwg, hipStream_t s) {
-  if (t.kc) hipLaunchKernelGGL((k_gemm_thin<KIND, KP, SP, true>), dim3(nwg), dim3(256), 0, s, t);
-  else hipLaunchKernelGGL((k_gemm_thin<KIND, KP, SP, false>), dim3(nwg), dim3(256), 0, s, t);
+  // 16-byte fragment loads need at least 2 complex k per lane (KP >= 8)
+  if constexpr (KP >= 8) {
+    if (t.kc) {
+      hipLaunchKernelGGL((k_gemm_thin<KIND, KP, SP, true>), dim3(nwg), dim3(256), 0, s, t);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm_thin<KIND, KP, SP, false>), dim3(nwg), dim3(256), 0, s, t);
 }
 
 template <int KIND>
 static void launch_thin_kind(const ThinArgs& t, unsigned nwg, hipStream_t s) {
+  // complex64 with K <= 4 or <= 8: a lane loads 1 or 2 complex k of a row (4 lanes cover the sum)
+  // instead of 4 slots of which the ones past K repeat the row's values
+  if constexpr (KIND == 0) {
+    if (t.K <= 4) {
+      if (t.S <= 16) launch_thin<KIND, 4, 16>(t, nwg, s);
+      else launch_thin<KIND, 4, 32>(t, nwg, s);
+      return;
+    }
+    if (t.K <= 8) {
+      if (t.S <= 16) launch_thin<KIND, 8, 16>(t, nwg, s);
+      else launch_thin<KIND, 8, 32>(t, nwg, s);
+      return;
+    }
+  }
   if (t.K <= 16) {
     if (t.S <= 16) launch_thin<KIND, 16, 16>(t, nwg, s);
     else launch_thin<KIND, 16, 32>(t, nwg, s);

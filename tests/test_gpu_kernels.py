@@ -127,11 +127,14 @@ def test_cgemm_tile_argument_validated():
                                            (512, 8, 8, True, False), (32, 333, 32, False, True),
                                            (5, 7, 3, True, True), (257, 31, 17, False, False),
                                            (2085, 16, 16, True, True), (20, 549, 24, True, False),
-                                           (1, 130, 1, True, True), (4096, 32, 32, True, True)])
+                                           (1, 130, 1, True, True), (4096, 32, 32, True, True),
+                                           (3000, 20, 5, False, True), (777, 4, 4, True, True),
+                                           (24, 300, 2, False, False), (1000, 32, 8, False, False)])
 def test_cgemm_thin_kernel(precision, M, N, K, akc, bkc):
     """The memory-bound thin kernel (a side of at most 32, K at most 32) on the 16x16 matrix-core shapes:
     ragged rows across blocks and waves, a short side of 1..32 (one or two 16-column blocks), K of 1..32
-    (one or two 16-k chunks), either operand the short one, k-contiguous or not."""
+    (one or two 16-k chunks; complex64 loads 1 or 2 k per lane for K up to 4 or 8), either operand the
+    short one, k-contiguous or not."""
     got, want, bound = _gemm_case(M, N, K, akc, bkc, 3, M * 3 + N * 5 + K, precision, "thin")
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     if precision == "c64":

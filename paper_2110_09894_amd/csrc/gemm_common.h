@@ -208,6 +208,14 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
   return tc;
 }
 
+// Complex64 product outputs are read by a later op, not by this one: their stores (each wave
+// instruction a run of consecutive elements) are non-temporal, so they do not displace the operand
+// panels the resident work-groups share in the L2.  Split outputs keep ordinary stores: a lane writes
+// a chunk's four planes in four instructions, which the L2 merges into whole lines.
+__device__ __forceinline__ void store_out(QxCplx* dst, QxCplx v) {
+  __builtin_nontemporal_store(qx_f32x2{v.x, v.y}, reinterpret_cast<qx_f32x2*>(dst));
+}
+
 // Orders this wave's LDS accesses before and after it (a wave's LDS operations
 // complete in issue order; the empty asm statements keep the compiler from
 // moving memory accesses across).  Unlike __syncthreads() it neither waits for
@@ -369,7 +377,7 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
         if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) {
           const QxCplx v = stage[lm * 33 + ln];
           if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), eb + off, v, KIND);
-          else p.c[eb + off] = v;
+          else store_out(p.c + eb + off, v);
         }
       };
       // a rolled loop keeps the FP32 kernel's registers low enough for two waves per SIMD

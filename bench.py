@@ -1014,6 +1014,9 @@ def main():
              "complex_tflops": executed / (elapsed / args.steps) / 1e12,
              "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
              "slice_batch": 1 << info["slice_batch_log2"], "timed_steps": "graph-replayed slice blocks"}
+        # work-group tiles of the largest matrix products (autotuned or default), largest first
+        prods = sorted((o for o in plan.ops() if o["op_class"] == "gemm"), key=lambda o: -o["flops"])
+        r["largest_product_tiles"] = [f"{o['M']}x{o['N']}x{o['K']}x{o['batch']}:{o['tile']}" for o in prods[:4]]
         if not args.no_timing:
             plan.set_timing(True)
             plan.get_timing(reset=True)

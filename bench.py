@@ -1055,7 +1055,7 @@ def main():
         "complex_tflops": main["complex_tflops"],
         "latency_ms": main["latency_ms"],
     }
-    for k in ("roofline", "time_by_class_ms_per_step", "evented_step_ms", "timed_steps"):
+    for k in ("roofline", "time_by_class_ms_per_step", "evented_step_ms", "timed_steps", "largest_product_tiles"):
         if k in main:
             out[k] = main[k]
     # contract calls each plan makes, in order (read by the trace summaries)

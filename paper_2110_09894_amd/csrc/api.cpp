@@ -473,6 +473,12 @@ static qx_status autotune_plan(qx_plan* p, hipStream_t s) {
       for (size_t c = 1; c < cand.size(); ++c)
         if (ms_min[c] < ms_min[bi]) bi = c;
       best = cand[bi];
+      if (getenv("QX_DUMP_TUNE")) {
+        fprintf(stderr, "tune prec %d M %lld N %lld K %lld items %d nh %d:", p->pc.precision, (long long)g.M,
+                (long long)g.N, (long long)g.K, g.n_items, g.nh);
+        for (size_t c = 0; c < cand.size(); ++c) fprintf(stderr, " t%d=%.3f", cand[c], ms_min[c]);
+        fprintf(stderr, " -> %d\n", best);
+      }
     }
     op.tile = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);

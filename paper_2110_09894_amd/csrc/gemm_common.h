@@ -210,8 +210,9 @@ __device__ inline TileCoord tile_coord(const GemmArgs& p, int BM, int BN) {
 
 // Complex64 product outputs are read by a later op, not by this one: their stores (each wave
 // instruction a run of consecutive elements) are non-temporal, so they do not displace the operand
-// panels the resident work-groups share in the L2.  Split outputs keep ordinary stores: a lane writes
-// a chunk's four planes in four instructions, which the L2 merges into whole lines.
+// panels the resident work-groups share in the L2.  The split kernels keep ordinary stores: a lane
+// writes a chunk's four planes in four instructions, which the L2 merges into whole lines (and the
+// non-temporal form in their unused complex64 branch made the 128x128 BF16 kernel spill).
 __device__ __forceinline__ void store_out(QxCplx* dst, QxCplx v) {
   __builtin_nontemporal_store(qx_f32x2{v.x, v.y}, reinterpret_cast<qx_f32x2*>(dst));
 }
@@ -246,7 +247,8 @@ __device__ __forceinline__ void split_scaled(QxCplx v, uint32_t& hi, uint32_t& l
 }
 
 // scale multiplies every accumulator before it is stored (split FP16: the output's scale over the
-// operands'); KIND is the split storage written when p.c_split is set.
+// operands'); KIND is the split storage written when p.c_split is set, 0 for the complex64 kernel
+// (whose products never write split storage, and whose plain stores are non-temporal).
 template <int FM, int FN, int WM, int WN, bool UNROLL, int KIND = 1>
 __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMap& om, int64_t m0,
                                     int64_t n0, int wm, int wn, int lane, const v16f (&cr)[FM][FN],
@@ -377,7 +379,8 @@ __device__ inline void store_blocks(const GemmArgs& p, int64_t coff, const OutMa
         if (m0 + lm0 + lm < p.M && n0 + ln0 + ln < p.N) {
           const QxCplx v = stage[lm * 33 + ln];
           if (p.c_split) store_split(reinterpret_cast<uint16_t*>(p.c), eb + off, v, KIND);
-          else store_out(p.c + eb + off, v);
+          else if constexpr (KIND == 0) store_out(p.c + eb + off, v);
+          else p.c[eb + off] = v;
         }
       };
       // a rolled loop keeps the FP32 kernel's registers low enough for two waves per SIMD

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256, (BM * BN > 64 * 64 && BM * BN <= 128 * 128) ? 
   }
 
   const OutMap om = out_map(p, m0, n0);
-  store_blocks<FM, FN, WM, WN, false>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, 1.f, smem + wave * (32 * 33));
+  store_blocks<FM, FN, WM, WN, false, 0>(p, tc.coff, om, m0, n0, wm, wn, lane, cr, ci, 1.f, smem + wave * (32 * 33));
 }
 
 template <int BM, int BN>
